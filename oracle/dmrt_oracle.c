@@ -1,0 +1,784 @@
+/*
+ * dmrt_oracle.c -- FP64 CPU oracle for the double-MRT lattice Boltzmann model
+ * of Liu & He (arXiv:1503.08406): D2Q9 MRT flow with the generalized non-Darcy
+ * force (Sec. 3.1), D2Q5 MRT temperature with the latent-heat source and the
+ * iterated enthalpy method (Sec. 3.2), non-equilibrium-extrapolation walls and
+ * a moving solid-liquid interface (Sec. 4, first paragraph).
+ *
+ * TEST INFRASTRUCTURE ONLY -- never linked into the product library.  It is
+ * written to be checked against the paper by eye: dense matrices M, M^-1, N,
+ * N^-1 exactly as printed, one function per equation, no fusion, no blocking.
+ * OpenMP splits loops over cells; it never changes the arithmetic of a cell.
+ *
+ * Readings where the paper is silent or garbled (each is listed with its
+ * reason in the design notes of the repository):
+ *   - Lambda = diag(1, s_e, s_eps, 1, s_q, 1, s_q, s_nu, s_nu) (Eq. (23)).
+ *   - Eq. (26) denominator starts with l_0 (the printed d_0 is a typo).
+ *   - rho0 replaces rho in the force terms (incompressible approximation).
+ *   - Eq. (6) is read in varphi = phi*f_l; the per-cell inputs K and F_eps are
+ *     the values at f_l = 1, so K_e = K (varphi/phi)^3 ((1-phi)/(1-varphi))^2
+ *     and C_e = F_eps (phi/varphi)^(3/2).  phi = 1 means clear fluid (no drag).
+ *   - The flow is solved where f_l > 0; a cell that becomes active restarts
+ *     at f_i = w_i rho0, a cell that becomes solid drops its populations.
+ *   - Boundaries: link-wise non-equilibrium extrapolation at the receiving
+ *     node.  A wall lies one lattice unit outside the first node.  A missing
+ *     population gets equilibrium(wall values) + (own post-collision value -
+ *     own equilibrium), with the start-of-step values of the receiving node.
+ *     Solid nodes act as no-slip walls for the flow.
+ *   - The latent source of Eq. (38) is applied after streaming at the
+ *     receiving node, so the enthalpy iteration is local to one cell.
+ *   - Enthalpy: c_ps = c_pl = 1, En_s = T_s, En_l = T_l + 1/St.
+ *   - sigma(f_l) = sigma_s + f_l (sigma_l - sigma_s) (Eq. (7) is linear in f_l);
+ *     alpha_e(f_l) = lambda alpha_l (f_l + (1-f_l)/(alpha_l/alpha_s)).
+ */
+#include "dmrt_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q9 9
+#define Q5 5
+
+static const double RHO0 = 1.0; /* Sec. 4: rho0 = 1 */
+static const double DT = 1.0;   /* Sec. 4: delta_t = 1 */
+static const double CS2 = 1.0 / 3.0; /* c_s = c / sqrt(3), Sec. 3.1 */
+
+/* Transformation matrix M, Eq. (18). */
+static const double M18[Q9][Q9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+/* Transformation matrix N, Eq. (32). */
+static const double N32[Q5][Q5] = {
+    {1, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0},
+    {0, 0, 1, 0, -1},
+    {-4, 1, 1, 1, 1},
+    {0, 1, -1, 1, -1}};
+
+typedef struct {
+    int ex[Q9], ey[Q9];
+    double w[Q9];
+    double M[Q9][Q9], Minv[Q9][Q9];
+} lat9;
+
+typedef struct {
+    int ex[Q5], ey[Q5];
+    double w[Q5];
+    double N[Q5][Q5], Ninv[Q5][Q5];
+} lat5;
+
+/* D2Q9: velocities from Eq. (15), weights below Eq. (29), M from Eq. (18),
+ * M^-1 = M^T (M M^T)^-1 as stated under Eq. (18). */
+static void build_lat9(lat9 *L)
+{
+    const double pi = acos(-1.0);
+    for (int i = 0; i < Q9; ++i) {
+        double ax = 0, ay = 0;
+        if (i >= 1 && i <= 4) {
+            ax = cos((i - 1) * pi / 2);
+            ay = sin((i - 1) * pi / 2);
+        } else if (i >= 5) {
+            ax = sqrt(2.0) * cos((2 * i - 9) * pi / 4);
+            ay = sqrt(2.0) * sin((2 * i - 9) * pi / 4);
+        }
+        L->ex[i] = (int)lround(ax);
+        L->ey[i] = (int)lround(ay);
+        L->w[i] = (i == 0) ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+    double MMt[Q9][Q9];
+    for (int a = 0; a < Q9; ++a)
+        for (int b = 0; b < Q9; ++b) {
+            double s = 0;
+            for (int k = 0; k < Q9; ++k) s += M18[a][k] * M18[b][k];
+            MMt[a][b] = s;
+        }
+    for (int a = 0; a < Q9; ++a)
+        for (int k = 0; k < Q9; ++k) {
+            L->M[a][k] = M18[a][k];
+            L->Minv[k][a] = M18[a][k] / MMt[a][a]; /* M M^T is diagonal */
+        }
+}
+
+/* D2Q5: velocities from Eq. (31), weights below Eq. (39), N from Eq. (32). */
+static void build_lat5(lat5 *L, double varpi)
+{
+    const double pi = acos(-1.0);
+    for (int i = 0; i < Q5; ++i) {
+        double ax = 0, ay = 0;
+        if (i >= 1) {
+            ax = cos((i - 1) * pi / 2);
+            ay = sin((i - 1) * pi / 2);
+        }
+        L->ex[i] = (int)lround(ax);
+        L->ey[i] = (int)lround(ay);
+        L->w[i] = (i == 0) ? (1.0 - varpi) / 5.0 : (4.0 + varpi) / 20.0;
+    }
+    double NNt[Q5][Q5];
+    for (int a = 0; a < Q5; ++a)
+        for (int b = 0; b < Q5; ++b) {
+            double s = 0;
+            for (int k = 0; k < Q5; ++k) s += N32[a][k] * N32[b][k];
+            NNt[a][b] = s;
+        }
+    for (int a = 0; a < Q5; ++a)
+        for (int k = 0; k < Q5; ++k) {
+            L->N[a][k] = N32[a][k];
+            L->Ninv[k][a] = N32[a][k] / NNt[a][a];
+        }
+}
+
+void orc_lattice(double varpi, int *ex9, int *ey9, double *w9, double *M,
+                 double *Minv, int *ex5, int *ey5, double *w5, double *N,
+                 double *Ninv)
+{
+    lat9 L9;
+    lat5 L5;
+    build_lat9(&L9);
+    build_lat5(&L5, varpi);
+    for (int i = 0; i < Q9; ++i) {
+        ex9[i] = L9.ex[i];
+        ey9[i] = L9.ey[i];
+        w9[i] = L9.w[i];
+        for (int k = 0; k < Q9; ++k) {
+            M[i * Q9 + k] = L9.M[i][k];
+            Minv[i * Q9 + k] = L9.Minv[i][k];
+        }
+    }
+    for (int i = 0; i < Q5; ++i) {
+        ex5[i] = L5.ex[i];
+        ey5[i] = L5.ey[i];
+        w5[i] = L5.w[i];
+        for (int k = 0; k < Q5; ++k) {
+            N[i * Q5 + k] = L5.N[i][k];
+            Ninv[i * Q5 + k] = L5.Ninv[i][k];
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Parameters                                                              */
+/* ---------------------------------------------------------------------- */
+
+void orc_default_params(orc_params *p)
+{
+    memset(p, 0, sizeof(*p));
+    p->nx = p->ny = 0;
+    p->H = 0;
+    for (int k = 0; k < 4; ++k) {
+        p->bc_kind[k] = ORC_WALL_ADIABATIC;
+        p->T_wall[k] = 0;
+    }
+    p->Ra = 0;
+    p->Da = 1e-4;
+    p->Pr = 1;
+    p->Ste = 1;
+    p->Ma = 0.1;      /* Sec. 4.3 */
+    p->J = 1;         /* Sec. 4 */
+    p->lambda_ = 1;
+    p->alpha_ratio = 1;
+    p->sigma_s = p->sigma_l = 1;
+    p->T_s = -0.02;   /* Sec. 4.1 / 4.2 mushy range around T_m = 0 */
+    p->T_l = 0.02;
+    p->T0 = 0;
+    p->T_init = 0;
+    p->alpha_l = 0.02; /* Sec. 4.1 */
+    p->varpi = -2;     /* Sec. 4 */
+    p->s_e = 1.1;      /* Sec. 4 */
+    p->s_eps = 1.1;
+    p->s_q = 1.2;
+    p->zeta_e = 1.5;
+    p->zeta_nu = 1.5;
+    p->ergun_c = 175;  /* Eq. (6) as printed */
+    p->fl_tol = 1e-12;
+    p->fl_maxit = 200;
+    p->convective = 1;
+    p->nthreads = 0;
+}
+
+static double sigma_of(const orc_params *p, double fl)
+{
+    return p->sigma_s + fl * (p->sigma_l - p->sigma_s);
+}
+
+int orc_derive(const orc_params *p, orc_derived *d)
+{
+    if (p->nx <= 0 || p->ny <= 0) return -1;
+    d->H = p->H > 0 ? p->H : (double)p->ny;
+    d->cs2 = CS2;
+    d->csT2 = (4.0 + p->varpi) / 10.0; /* below Eq. (39), c = 1 */
+    if (p->Ra > 0) {
+        /* Sec. 4.3: tau_nu = 1/2 + Ma J H sqrt(3 Pr) / (c dt sqrt(Ra)) */
+        d->tau_nu = 0.5 + p->Ma * p->J * d->H * sqrt(3.0 * p->Pr) / (DT * sqrt(p->Ra));
+        d->nu_e = CS2 * (d->tau_nu - 0.5) * DT; /* below Eq. (28) */
+        d->nu_l = d->nu_e / p->J;               /* J = nu_e / nu_l, Eq. (9) */
+        d->alpha_l = d->nu_l / p->Pr;           /* Pr = nu_l / alpha_l */
+        /* Ma = u_c / c_s with u_c = sqrt(g beta DeltaT H), Sec. 4.3 */
+        double uc = p->Ma * sqrt(CS2);
+        d->gbeta = uc * uc / d->H;
+    } else {
+        d->alpha_l = p->alpha_l;
+        d->nu_l = p->Pr * d->alpha_l;
+        d->nu_e = p->J * d->nu_l;
+        d->tau_nu = 0.5 + d->nu_e / (CS2 * DT);
+        d->gbeta = 0;
+    }
+    d->alpha_s = d->alpha_l / p->alpha_ratio;
+    d->K_default = p->Da * d->H * d->H; /* Da = K / H^2, Eq. (9) */
+    /* tau_T = 1/2 + alpha_e / (sigma c_sT^2 dt), below Eq. (39) and Sec. 4.1 */
+    d->tau_T_liquid = 0.5 + p->lambda_ * d->alpha_l / (p->sigma_l * d->csT2 * DT);
+    d->tau_T_solid = 0.5 + p->lambda_ * d->alpha_s / (p->sigma_s * d->csT2 * DT);
+    if (!(d->tau_nu > 0.5) || !(d->tau_T_liquid > 0.5) || !(d->tau_T_solid > 0.5))
+        return -2;
+    return 0;
+}
+
+/* alpha_e(f_l) = alpha_l f_l + alpha_s (1 - f_l), scaled by lambda (Sec. 4.1, 4.3). */
+static double tauT_of(const orc_params *p, const orc_derived *d, double fl)
+{
+    double alpha_e = p->lambda_ * (d->alpha_l * fl + d->alpha_s * (1.0 - fl));
+    return 0.5 + alpha_e / (sigma_of(p, fl) * d->csT2 * DT);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Per-cell operators                                                      */
+/* ---------------------------------------------------------------------- */
+
+static lat9 G9; /* D2Q9 tables, built once when the library is loaded */
+static lat5 G5; /* D2Q5 velocities (weights depend on varpi: see w5_of) */
+
+__attribute__((constructor)) static void build_tables(void)
+{
+    build_lat9(&G9);
+    build_lat5(&G5, -2.0);
+}
+
+/* D2Q5 weights below Eq. (39). */
+static double w5_of(int i, double varpi)
+{
+    return i == 0 ? (1.0 - varpi) / 5.0 : (4.0 + varpi) / 20.0;
+}
+
+/* Eq. (29) */
+void orc_feq(double rho, double ux, double uy, double phi, double *feq9)
+{
+    double uu = ux * ux + uy * uy;
+    for (int i = 0; i < Q9; ++i) {
+        double eu = G9.ex[i] * ux + G9.ey[i] * uy;
+        feq9[i] = G9.w[i] * (rho + RHO0 * (eu / CS2 + eu * eu / (2 * CS2 * CS2 * phi) -
+                                           uu / (2 * CS2 * phi)));
+    }
+}
+
+/* Eq. (19) */
+void orc_meq(double rho, double ux, double uy, double phi, double *m)
+{
+    double uu = ux * ux + uy * uy;
+    m[0] = rho;
+    m[1] = -2 * rho + 3 * RHO0 * uu / phi;
+    m[2] = rho - 3 * RHO0 * uu / phi;
+    m[3] = RHO0 * ux;
+    m[4] = -RHO0 * ux;
+    m[5] = RHO0 * uy;
+    m[6] = -RHO0 * uy;
+    m[7] = RHO0 * (ux * ux - uy * uy) / phi;
+    m[8] = RHO0 * ux * uy / phi;
+}
+
+/* Eq. (22) */
+void orc_force_moments(double ux, double uy, double Fx, double Fy, double phi, double *S)
+{
+    double uF = ux * Fx + uy * Fy;
+    S[0] = 0;
+    S[1] = 6 * RHO0 * uF / phi;
+    S[2] = -6 * RHO0 * uF / phi;
+    S[3] = RHO0 * Fx;
+    S[4] = -RHO0 * Fx;
+    S[5] = RHO0 * Fy;
+    S[6] = -RHO0 * Fy;
+    S[7] = 2 * RHO0 * (ux * Fx - uy * Fy) / phi;
+    S[8] = RHO0 * (ux * Fy + uy * Fx) / phi;
+}
+
+/* Eq. (39) */
+void orc_geq(double T, double ux, double uy, double sigma, double varpi, double *geq5)
+{
+    double csT2 = (4.0 + varpi) / 10.0;
+    for (int i = 0; i < Q5; ++i) {
+        double eu = G5.ex[i] * ux + G5.ey[i] * uy;
+        geq5[i] = w5_of(i, varpi) * T * (1.0 + eu / (sigma * csT2));
+    }
+}
+
+/* Eq. (34) */
+void orc_neq(double T, double ux, double uy, double sigma, double varpi, int convective,
+             double *n)
+{
+    double th = convective ? 1.0 : 0.0;
+    n[0] = T;
+    n[1] = th * ux * T / sigma;
+    n[2] = th * uy * T / sigma;
+    n[3] = varpi * T;
+    n[4] = 0;
+}
+
+/* Eq. (20), then f+ = M^-1 m+ (text below Eq. (21)). */
+void orc_collide_f(const double *f, double rho, double ux, double uy, double Fx, double Fy,
+                   double phi, const double *s, double *fpost)
+{
+    double m[Q9], meq[Q9], S[Q9], mp[Q9];
+    for (int a = 0; a < Q9; ++a) {
+        double v = 0;
+        for (int i = 0; i < Q9; ++i) v += G9.M[a][i] * f[i];
+        m[a] = v; /* Eq. (16) */
+    }
+    orc_meq(rho, ux, uy, phi, meq);
+    orc_force_moments(ux, uy, Fx, Fy, phi, S);
+    for (int a = 0; a < Q9; ++a)
+        mp[a] = m[a] - s[a] * (m[a] - meq[a]) + DT * (1.0 - s[a] / 2.0) * S[a];
+    for (int i = 0; i < Q9; ++i) {
+        double v = 0;
+        for (int a = 0; a < Q9; ++a) v += G9.Minv[i][a] * mp[a];
+        fpost[i] = v;
+    }
+}
+
+/* Eqs. (27), (28), (26) and the total force Eq. (4). */
+void orc_closure(double jx, double jy, double phi, double nu_l, double Ke, double Ce,
+                 double Gx, double Gy, double *u, double *F)
+{
+    double vx = jx / RHO0 + DT / 2 * phi * Gx; /* Eq. (27) */
+    double vy = jy / RHO0 + DT / 2 * phi * Gy;
+    if (!(Ke > 0)) {
+        /* Vanishing permeability: infinite drag, u = 0; Eq. (25) then fixes F. */
+        u[0] = u[1] = 0;
+        F[0] = -2 * jx / (DT * RHO0);
+        F[1] = -2 * jy / (DT * RHO0);
+        return;
+    }
+    double l0 = 0.5 * (1.0 + phi * DT / 2 * nu_l / Ke); /* Eq. (28) */
+    double l1 = phi * DT / 2 * Ce / sqrt(Ke);
+    double vmag = sqrt(vx * vx + vy * vy);
+    double den = l0 + sqrt(l0 * l0 + l1 * vmag); /* Eq. (26) */
+    u[0] = vx / den;
+    u[1] = vy / den;
+    double umag = sqrt(u[0] * u[0] + u[1] * u[1]);
+    /* Eq. (4) */
+    F[0] = -phi * nu_l / Ke * u[0] - phi * Ce / sqrt(Ke) * umag * u[0] + phi * Gx;
+    F[1] = -phi * nu_l / Ke * u[1] - phi * Ce / sqrt(Ke) * umag * u[1] + phi * Gy;
+}
+
+/* Eq. (41): temperature from total enthalpy (c_ps = c_pl = 1). */
+static double T_of_En(double En, double T_s, double T_l, double Ste)
+{
+    double En_s = T_s;             /* c_ps T_s */
+    double En_l = T_l + 1.0 / Ste; /* c_pl T_l + L_a, L_a / c_pl = 1/St */
+    if (En <= En_s) return En;
+    if (En >= En_l) return T_l + (En - En_l);
+    return T_s + (En - En_s) / (En_l - En_s) * (T_l - T_s);
+}
+
+/* Eq. (42) */
+static double fl_of_T(double T, double T_s, double T_l)
+{
+    if (T <= T_s) return 0.0;
+    if (T >= T_l) return 1.0;
+    return (T - T_s) / (T_l - T_s);
+}
+
+/* Iterated enthalpy method (Sec. 3.2, end): the latent source of Eq. (38)
+ * needs f_l(t+dt); iterate T <- T* + S0(f), En (Eq. 40), T(En) (Eq. 41),
+ * f_l(T) (Eq. 42) until f_l stops changing. */
+int orc_enthalpy(double Tstar, double fl_old, double eps, double Ste, double sigma_s,
+                 double sigma_l, double T_s, double T_l, double tol, int maxit,
+                 double *fl_new, double *T_new)
+{
+    double f = fl_old;
+    int it = 0;
+    while (it < maxit) {
+        ++it;
+        double sig = sigma_s + f * (sigma_l - sigma_s);
+        double S0 = -(eps / (sig * Ste)) * (f - fl_old) / DT; /* Eq. (38) */
+        double T = Tstar + DT * S0;                            /* zeroth moment of Eq. (35) */
+        double En = T + f / Ste;                               /* Eq. (40) */
+        double fn = fl_of_T(T_of_En(En, T_s, T_l, Ste), T_s, T_l);
+        int done = fabs(fn - f) <= tol;
+        f = fn;
+        if (done) break;
+    }
+    double sig = sigma_s + f * (sigma_l - sigma_s);
+    *fl_new = f;
+    *T_new = Tstar - DT * (eps / (sig * Ste)) * (f - fl_old) / DT;
+    return it;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Simulation                                                              */
+/* ---------------------------------------------------------------------- */
+
+struct orc_sim {
+    orc_params p;
+    orc_derived d;
+    lat9 L9;
+    lat5 L5;
+    int nx, ny;
+    long nc, t;
+    double *eps, *K, *Feps;
+    double *f, *g, *fl;               /* state: f[c*9+i], g[c*5+i], fl[c] */
+    double *fpost, *gpost, *fnew, *gnew, *flnew;
+    double *T, *ux, *uy, *rho, *Fx, *Fy;
+    unsigned char *chi;
+    int *iters;
+};
+
+#define NT(s) ((s)->p.nthreads > 0 ? (s)->p.nthreads : 1)
+
+static double *dalloc(long n)
+{
+    double *a = (double *)calloc((size_t)n, sizeof(double));
+    return a;
+}
+
+orc_sim *orc_create(const orc_params *p, const double *eps, const double *K,
+                    const double *Feps)
+{
+    orc_derived d;
+    if (!eps || orc_derive(p, &d) != 0) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->p = *p;
+    s->d = d;
+    build_lat9(&s->L9);
+    build_lat5(&s->L5, p->varpi);
+    s->nx = p->nx;
+    s->ny = p->ny;
+    s->nc = (long)p->nx * p->ny;
+    long nc = s->nc;
+    s->eps = dalloc(nc);
+    s->K = dalloc(nc);
+    s->Feps = dalloc(nc);
+    s->f = dalloc(nc * Q9);
+    s->g = dalloc(nc * Q5);
+    s->fl = dalloc(nc);
+    s->fpost = dalloc(nc * Q9);
+    s->gpost = dalloc(nc * Q5);
+    s->fnew = dalloc(nc * Q9);
+    s->gnew = dalloc(nc * Q5);
+    s->flnew = dalloc(nc);
+    s->T = dalloc(nc);
+    s->ux = dalloc(nc);
+    s->uy = dalloc(nc);
+    s->rho = dalloc(nc);
+    s->Fx = dalloc(nc);
+    s->Fy = dalloc(nc);
+    s->chi = (unsigned char *)calloc((size_t)nc, 1);
+    s->iters = (int *)calloc((size_t)nc, sizeof(int));
+    for (long c = 0; c < nc; ++c) {
+        s->eps[c] = eps[c];
+        s->K[c] = K ? K[c] : d.K_default;
+        /* Eq. (6) at f_l = 1 */
+        s->Feps[c] = Feps ? Feps[c] : 1.75 / sqrt(p->ergun_c * pow(eps[c], 3));
+    }
+    /* Initial state: uniform T_init at rest.  g = g^eq(T, 0) (Eq. 39),
+     * f_l = f_l(T) (Eq. 42), f = f^eq(rho0, 0) (Eq. 29) where liquid. */
+    for (long c = 0; c < nc; ++c) {
+        double T = p->T_init;
+        for (int i = 0; i < Q5; ++i) s->g[c * Q5 + i] = s->L5.w[i] * T;
+        s->fl[c] = fl_of_T(T, p->T_s, p->T_l);
+        for (int i = 0; i < Q9; ++i) s->f[c * Q9 + i] = s->fl[c] > 0 ? s->L9.w[i] * RHO0 : 0.0;
+    }
+    s->t = 0;
+    return s;
+}
+
+void orc_destroy(orc_sim *s)
+{
+    if (!s) return;
+    free(s->eps); free(s->K); free(s->Feps);
+    free(s->f); free(s->g); free(s->fl);
+    free(s->fpost); free(s->gpost); free(s->fnew); free(s->gnew); free(s->flnew);
+    free(s->T); free(s->ux); free(s->uy); free(s->rho); free(s->Fx); free(s->Fy);
+    free(s->chi); free(s->iters);
+    free(s);
+}
+
+void orc_set_state(orc_sim *s, const double *f, const double *g, const double *fl)
+{
+    long nc = s->nc;
+    for (long c = 0; c < nc; ++c) {
+        for (int i = 0; i < Q9; ++i) s->f[c * Q9 + i] = f[i * nc + c];
+        for (int i = 0; i < Q5; ++i) s->g[c * Q5 + i] = g[i * nc + c];
+        s->fl[c] = fl[c];
+    }
+}
+
+void orc_get_state(const orc_sim *s, double *f, double *g, double *fl)
+{
+    long nc = s->nc;
+    for (long c = 0; c < nc; ++c) {
+        for (int i = 0; i < Q9; ++i) f[i * nc + c] = s->f[c * Q9 + i];
+        for (int i = 0; i < Q5; ++i) g[i * nc + c] = s->g[c * Q5 + i];
+        fl[c] = s->fl[c];
+    }
+}
+
+long orc_time(const orc_sim *s) { return s->t; }
+
+/* Effective permeability and inertial coefficient at varphi = eps*fl. */
+static void porous_at(double eps, double K, double Feps, double fl, double *Ke, double *Ce)
+{
+    if (eps >= 1.0) { /* clear fluid: no porous drag */
+        *Ke = INFINITY;
+        *Ce = 0.0;
+        return;
+    }
+    double phi = eps * fl;
+    *Ke = K * pow(phi / eps, 3) * pow((1.0 - eps) / (1.0 - phi), 2);
+    *Ce = Feps * pow(eps / phi, 1.5);
+}
+
+/* Step 1: macroscopic quantities of cell c from the state. */
+static void macros_cell(const orc_sim *s, const double *f, const double *g,
+                        const double *fl, long c, double *T, double *rho, double *ux,
+                        double *uy, double *Fx, double *Fy, unsigned char *chi)
+{
+    double Tc = 0;
+    for (int i = 0; i < Q5; ++i) Tc += g[c * Q5 + i]; /* Eq. (33) */
+    *T = Tc;
+    *chi = fl[c] > 0;
+    if (!*chi) {
+        *rho = 0;
+        *ux = *uy = *Fx = *Fy = 0;
+        return;
+    }
+    double r = 0, jx = 0, jy = 0;
+    for (int i = 0; i < Q9; ++i) {
+        double fi = f[c * Q9 + i];
+        r += fi;                       /* Eq. (24) */
+        jx += s->L9.ex[i] * fi;
+        jy += s->L9.ey[i] * fi;
+    }
+    double phi = s->eps[c] * fl[c];
+    double Ke, Ce;
+    porous_at(s->eps[c], s->K[c], s->Feps[c], fl[c], &Ke, &Ce);
+    double Gy = s->d.gbeta * (Tc - s->p.T0); /* Eq. (5), +y */
+    double u[2], F[2];
+    orc_closure(jx, jy, phi, s->d.nu_l, Ke, Ce, 0.0, Gy, u, F);
+    *rho = r;
+    *ux = u[0];
+    *uy = u[1];
+    *Fx = F[0];
+    *Fy = F[1];
+}
+
+/* Steps 2-3: collisions of cell c (f only where chi). */
+static void collide_cell(const orc_sim *s, const double *f, const double *g,
+                         const double *fl, long c, double T, double rho, double ux,
+                         double uy, double Fx, double Fy, int chi, double *fpost,
+                         double *gpost)
+{
+    const orc_params *p = &s->p;
+    if (chi) {
+        double sv[Q9] = {1, p->s_e, p->s_eps, 1, p->s_q, 1, p->s_q,
+                         1.0 / s->d.tau_nu, 1.0 / s->d.tau_nu}; /* Eq. (23), Sec. 4 */
+        double phi = s->eps[c] * fl[c];
+        orc_collide_f(&f[c * Q9], rho, ux, uy, Fx, Fy, phi, sv, &fpost[c * Q9]);
+    } else {
+        for (int i = 0; i < Q9; ++i) fpost[c * Q9 + i] = 0;
+    }
+    /* D2Q5, Eqs. (32), (34), (35), (37); the source is added after streaming. */
+    double sig = sigma_of(p, fl[c]);
+    double za = 1.0 / tauT_of(p, &s->d, fl[c]);
+    double theta[Q5] = {1, za, za, p->zeta_e, p->zeta_nu};
+    double n[Q5], neq[Q5], np[Q5];
+    for (int a = 0; a < Q5; ++a) {
+        double v = 0;
+        for (int i = 0; i < Q5; ++i) v += s->L5.N[a][i] * g[c * Q5 + i];
+        n[a] = v;
+    }
+    orc_neq(T, ux, uy, sig, p->varpi, p->convective, neq);
+    for (int a = 0; a < Q5; ++a) np[a] = n[a] - theta[a] * (n[a] - neq[a]);
+    for (int i = 0; i < Q5; ++i) {
+        double v = 0;
+        for (int a = 0; a < Q5; ++a) v += s->L5.Ninv[i][a] * np[a];
+        gpost[c * Q5 + i] = v;
+    }
+}
+
+/* Locate the source x - e_i of a pull.  Returns 1 and the wrapped node if it
+ * is a lattice node; 0 and the wall side if it lies outside. */
+static int source_node(const orc_sim *s, int x, int y, int ex, int ey, int *sx, int *sy,
+                       int *side)
+{
+    int X = x - ex, Y = y - ey, out = 0;
+    *side = -1;
+    if (X < 0) {
+        if (s->p.bc_kind[0] == ORC_PERIODIC) X += s->nx; else { out = 1; *side = 0; }
+    } else if (X >= s->nx) {
+        if (s->p.bc_kind[1] == ORC_PERIODIC) X -= s->nx; else { out = 1; *side = 1; }
+    }
+    if (Y < 0) {
+        if (s->p.bc_kind[2] == ORC_PERIODIC) Y += s->ny; else { if (!out) *side = 2; out = 1; }
+    } else if (Y >= s->ny) {
+        if (s->p.bc_kind[3] == ORC_PERIODIC) Y -= s->ny; else { if (!out) *side = 3; out = 1; }
+    }
+    *sx = X;
+    *sy = Y;
+    return !out;
+}
+
+static void one_step(orc_sim *s)
+{
+    const orc_params *p = &s->p;
+    const int nx = s->nx, ny = s->ny;
+    const long nc = s->nc;
+    const int nt = NT(s);
+
+    /* Step 1: macros at time k (chi^k = [f_l^k > 0]). */
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long c = 0; c < nc; ++c)
+        macros_cell(s, s->f, s->g, s->fl, c, &s->T[c], &s->rho[c], &s->ux[c], &s->uy[c],
+                    &s->Fx[c], &s->Fy[c], &s->chi[c]);
+
+    /* Steps 2-3: collisions. */
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long c = 0; c < nc; ++c)
+        collide_cell(s, s->f, s->g, s->fl, c, s->T[c], s->rho[c], s->ux[c], s->uy[c],
+                     s->Fx[c], s->Fy[c], s->chi[c], s->fpost, s->gpost);
+
+    /* Steps 4-5: streaming, Eqs. (21) and (36), pull form, with non-equilibrium
+     * extrapolation for sources that are walls (g, f) or solid nodes (f). */
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            long c = (long)y * nx + x;
+            int sx, sy, side;
+            double sig = sigma_of(p, s->fl[c]);
+            double geq_x[Q5];
+            orc_geq(s->T[c], s->ux[c], s->uy[c], sig, p->varpi, geq_x);
+            for (int i = 0; i < Q5; ++i) {
+                if (source_node(s, x, y, s->L5.ex[i], s->L5.ey[i], &sx, &sy, &side)) {
+                    s->gnew[c * Q5 + i] = s->gpost[((long)sy * nx + sx) * Q5 + i];
+                } else {
+                    double Tw = p->bc_kind[side] == ORC_WALL_T ? p->T_wall[side] : s->T[c];
+                    double geq_w[Q5];
+                    orc_geq(Tw, 0, 0, sig, p->varpi, geq_w);
+                    s->gnew[c * Q5 + i] = geq_w[i] + s->gpost[c * Q5 + i] - geq_x[i];
+                }
+            }
+            if (!s->chi[c]) {
+                for (int i = 0; i < Q9; ++i) s->fnew[c * Q9 + i] = 0;
+                continue;
+            }
+            double phi = s->eps[c] * s->fl[c];
+            double feq_x[Q9], feq_w[Q9];
+            orc_feq(s->rho[c], s->ux[c], s->uy[c], phi, feq_x);
+            orc_feq(s->rho[c], 0, 0, phi, feq_w);
+            for (int i = 0; i < Q9; ++i) {
+                long sc;
+                if (source_node(s, x, y, s->L9.ex[i], s->L9.ey[i], &sx, &sy, &side) &&
+                    s->chi[sc = (long)sy * nx + sx]) {
+                    s->fnew[c * Q9 + i] = s->fpost[sc * Q9 + i];
+                } else {
+                    s->fnew[c * Q9 + i] = feq_w[i] + s->fpost[c * Q9 + i] - feq_x[i];
+                }
+            }
+        }
+    }
+
+    /* Step 6: iterated enthalpy method and the latent source N^-1 dt S~
+     * (Eqs. 30, 38, 40-42), at the receiving node. */
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        double Tstar = 0;
+        for (int i = 0; i < Q5; ++i) Tstar += s->gnew[c * Q5 + i];
+        double fln, Tn;
+        s->iters[c] = orc_enthalpy(Tstar, s->fl[c], s->eps[c], p->Ste, p->sigma_s,
+                                   p->sigma_l, p->T_s, p->T_l, p->fl_tol, p->fl_maxit,
+                                   &fln, &Tn);
+        double sig = sigma_of(p, fln);
+        double St[Q5] = {0, 0, 0, 0, 0};
+        St[0] = -(s->eps[c] / (sig * p->Ste)) * (fln - s->fl[c]) / DT; /* Eq. (38) */
+        St[3] = p->varpi * St[0];
+        for (int i = 0; i < Q5; ++i) {
+            double v = 0;
+            for (int a = 0; a < Q5; ++a) v += s->L5.Ninv[i][a] * St[a];
+            s->gnew[c * Q5 + i] += DT * v;
+        }
+        s->flnew[c] = fln;
+    }
+
+    /* Step 7: flow mask update. */
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        int was = s->fl[c] > 0, now = s->flnew[c] > 0;
+        for (int i = 0; i < Q9; ++i) {
+            if (now && !was) s->fnew[c * Q9 + i] = s->L9.w[i] * RHO0;
+            else if (!now) s->fnew[c * Q9 + i] = 0;
+        }
+    }
+
+    double *tmp;
+    tmp = s->f; s->f = s->fnew; s->fnew = tmp;
+    tmp = s->g; s->g = s->gnew; s->gnew = tmp;
+    tmp = s->fl; s->fl = s->flnew; s->flnew = tmp;
+    s->t += 1;
+}
+
+void orc_step(orc_sim *s, long n)
+{
+    for (long k = 0; k < n; ++k) one_step(s);
+}
+
+void orc_fields(const orc_sim *s, double *T, double *ux, double *uy, double *fl, double *rho)
+{
+    const long nc = s->nc;
+#pragma omp parallel for num_threads(NT(s)) schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        double t, r, a, b, fx, fy;
+        unsigned char chi;
+        macros_cell(s, s->f, s->g, s->fl, c, &t, &r, &a, &b, &fx, &fy, &chi);
+        if (T) T[c] = t;
+        if (ux) ux[c] = a;
+        if (uy) uy[c] = b;
+        if (fl) fl[c] = s->fl[c];
+        if (rho) rho[c] = r;
+    }
+}
+
+void orc_post_collision(const orc_sim *s, double *fpost, double *gpost)
+{
+    const long nc = s->nc;
+    double *fp = dalloc(nc * Q9), *gp = dalloc(nc * Q5);
+#pragma omp parallel for num_threads(NT(s)) schedule(static)
+    for (long c = 0; c < nc; ++c) {
+        double t, r, a, b, fx, fy;
+        unsigned char chi;
+        macros_cell(s, s->f, s->g, s->fl, c, &t, &r, &a, &b, &fx, &fy, &chi);
+        collide_cell(s, s->f, s->g, s->fl, c, t, r, a, b, fx, fy, chi, fp, gp);
+    }
+    for (long c = 0; c < nc; ++c) {
+        for (int i = 0; i < Q9; ++i) fpost[i * nc + c] = fp[c * Q9 + i];
+        for (int i = 0; i < Q5; ++i) gpost[i * nc + c] = gp[c * Q5 + i];
+    }
+    free(fp);
+    free(gp);
+}
+
+void orc_iter_stats(const orc_sim *s, long *max_it, long *sum_it)
+{
+    long mx = 0, sm = 0;
+    for (long c = 0; c < s->nc; ++c) {
+        if (s->iters[c] > mx) mx = s->iters[c];
+        sm += s->iters[c];
+    }
+    *max_it = mx;
+    *sum_it = sm;
+}
