@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of the fused double-MRT step (flow + thermal + enthalpy) on one
+MI355X, on the convection-melting cavity workload: 1024x1024 lattice, hot
+left wall, cold right wall, adiabatic top/bottom, Ra = 1e6, Da = 1e-4,
+Pr = 1, Ste = 1, porosity 0.4 with a seeded log-normal permeability
+(sigma 0.1), initially solid (Sec. 4.3 setting at a new size).
+
+Prints one JSON line: MLUPS over the timed steps, the roofline of the step
+kernel (HIP events on the solver's stream), and the FP64 oracle timed on a
+bounded sample on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+# Algorithmic bytes per cell update (float32): a cell where the flow is solved
+# reads and writes its 9 + 5 populations and f_l and reads the three porous
+# fields; a solid cell moves only the 5 thermal populations, f_l and porosity.
+BYTES_FLUID = 2 * (9 + 5) * 4 + 2 * 4 + 3 * 4   # 132
+BYTES_SOLID = 2 * 5 * 4 + 2 * 4 + 4             # 52
+KERNEL_SRC = os.path.join(ROOT, "paper_1503_08406_amd", "csrc", "dmrt_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic_cavity1024.json")
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def cpu_baseline(case, budget_s=15.0):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from conftest import oracle_from_case
+    cores = min(16, len(os.sched_getaffinity(0)))
+    o = oracle_from_case(case, nthreads=cores)
+    t = time.perf_counter()
+    o.step(5)
+    dt = (time.perf_counter() - t) / 5
+    n = max(5, min(2000, int(budget_s / max(dt, 1e-6))))
+    t = time.perf_counter()
+    o.step(n)
+    el = time.perf_counter() - t
+    cells = case["nx"] * case["ny"]
+    return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": "steps 5..%d of the %dx%d cavity from its initial state (FP64 oracle, "
+                      "%d OpenMP threads, %.1f s)" % (5 + n, case["nx"], case["ny"], cores, el)}
+
+
+def active_cell_steps(case, steps, samples, **over):
+    """Untimed replay: integral over the timed steps of the number of cells
+    where the flow is solved (trapezoid over `samples` points)."""
+    from paper_1503_08406_amd.dmrt import Solver
+    s = Solver(case, **over)
+    pts = [(0, s.diag()["active"])]
+    for k in range(1, samples + 1):
+        tgt = steps * k // samples
+        s.step(tgt - s.time)
+        pts.append((tgt, s.diag()["active"]))
+    tot = 0.0
+    for (t0, a0), (t1, a1) in zip(pts, pts[1:]):
+        tot += 0.5 * (a0 + a1) * (t1 - t0)
+    s.close()
+    return tot, pts[-1][1]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--n", type=int, default=1024, help="lattice side")
+    ap.add_argument("--graph-steps", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-account", action="store_true", help="skip the phase accounting replay")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1503_08406_amd import workloads as W
+    from paper_1503_08406_amd.dmrt import Solver
+
+    torch.cuda.set_device(0)
+    case = W.cavity(nx=args.n, ny=args.n, steps=args.steps)
+    over = dict(graph_steps=args.graph_steps)
+
+    if args.copy_probe:
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("copy probe: 3 x 1 GiB device-to-device copies", flush=True)
+
+    # warm-up on a throw-away solver, then time the workload from t = 0
+    w = Solver(case, **over)
+    w.step(args.warmup)
+    w.sync()
+    w.close()
+    s = Solver(case, **over)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(s.stream)
+    s.step(args.steps)
+    ev1.record(s.stream)
+    s.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kern_ms = ev0.elapsed_time(ev1) / args.steps
+    d = s.diag()
+    assert d["nonfinite"] == 0, "non-finite state after the timed run"
+    cells = case["nx"] * case["ny"]
+    mlups = cells * args.steps / wall / 1e6
+
+    if args.no_account:
+        act_steps, act_end = float(d["active"]) * args.steps, d["active"]
+    else:
+        act_steps, act_end = active_cell_steps(case, args.steps, 50, **over)
+    fluid_frac = act_steps / (cells * args.steps)
+    bytes_per_launch = (BYTES_FLUID * fluid_frac + BYTES_SOLID * (1 - fluid_frac)) * cells
+    achieved = bytes_per_launch / (kern_ms * 1e-3)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_sha") == kernel_hash() and tr.get("steps") == args.steps:
+            traffic = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": "MLUPS (flow+thermal)",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "convection melting in a porous cavity %dx%d (Sec. 4.3 setting): "
+                               "Ra=1e6 Da=1e-4 Pr=1 Ste=1 eps=0.4, log-normal K (sigma 0.1, "
+                               "seed 3), initially solid, steps 0..%d"
+                               % (args.n, args.n, args.steps),
+                   "nx": args.n, "ny": args.n, "graph_steps": args.graph_steps,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
+                     "traffic": traffic,
+                     "kernel": "k_step<flow>", "kernel_ms": round(kern_ms, 6),
+                     "bytes_per_launch": round(bytes_per_launch),
+                     "fluid_fraction_mean": round(fluid_frac, 5),
+                     "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID}},
+        "phase": {"active_cells_end": int(act_end), "front_mean_end": round(d["front_mean"], 3)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

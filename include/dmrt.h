@@ -1,0 +1,192 @@
+/*
+ * dmrt.h -- C ABI of the MI355X double-MRT lattice Boltzmann solver for
+ * solid-liquid phase change with natural convection in porous media
+ * (Liu & He, arXiv:1503.08406).
+ *
+ * One time step is one fused pass over the lattice: pull-streaming of the
+ * D2Q9 flow populations (Eq. 21) and D2Q5 temperature populations (Eq. 36),
+ * non-equilibrium-extrapolation walls and the moving solid-liquid interface
+ * (Sec. 4, first paragraph), the iterated enthalpy update with the latent
+ * source (Eqs. 38, 40-42), the velocity closure and porous force (Eqs. 4-6,
+ * 24-28), the D2Q9 MRT collision with forcing (Eqs. 17-20, 22-23) and the
+ * D2Q5 MRT collision (Eqs. 32-35, 37, 39).
+ *
+ * Units: lattice units, dx = dt = c = 1, rho0 = 1 (Sec. 4).  Temperatures are
+ * the dimensionless theta of Eq. (9) (Delta T = 1, so L_a/c_p = 1/St).
+ *
+ * Conventions for every entry point:
+ *  - Return 0 (DMRT_OK) on success or a negative DMRT_E* code; nothing is
+ *    thrown and nothing aborts.  dmrt_last_error() gives a thread-local text
+ *    for the last failure on the calling thread.
+ *  - Scalar fields are [ny][nx] float32 with index y*nx + x; population arrays
+ *    are planar [q][ny][nx].  Every field pointer may be host memory or device
+ *    memory of the handle's device (the library asks the HIP runtime which).
+ *  - The library copies what it needs at create time; the caller keeps
+ *    ownership of every pointer it passes.  All device state belongs to the
+ *    handle and is released by dmrt_destroy.
+ *  - Work is enqueued on the stream given in dmrt_opts (NULL: the null
+ *    stream).  Calls that return data to the caller synchronise that stream.
+ *  - A handle is not thread-safe; different handles are independent.
+ */
+#ifndef DMRT_H
+#define DMRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DMRT_OK 0
+#define DMRT_EINVAL (-1)     /* bad argument, size or parameter            */
+#define DMRT_ENOMEM (-2)     /* device or host allocation failed           */
+#define DMRT_EDEVICE (-3)    /* a HIP runtime call failed                  */
+#define DMRT_ENONFINITE (-4) /* the state holds NaN/Inf (see check_every)  */
+#define DMRT_ESIZE (-5)      /* caller buffer too small                    */
+
+/* Boundary kinds; every wall is a no-slip wall for the flow (Sec. 4). */
+typedef enum {
+    DMRT_PERIODIC = 0,       /* both sides of the axis must be periodic     */
+    DMRT_WALL_T = 1,         /* wall held at T_wall (Secs. 4.1-4.3)         */
+    DMRT_WALL_ADIABATIC = 2  /* wall at the receiving node's temperature    */
+} dmrt_bc_kind;
+
+/* Lattice of nx * ny evolving nodes.  A non-periodic side has its wall one
+ * lattice unit outside the first/last node.  H is the characteristic length
+ * of Eq. (9); H <= 0 means H = ny (Sec. 4.3). */
+typedef struct {
+    int32_t nx, ny;
+    double H;
+} dmrt_grid;
+
+/* Sides are ordered x-, x+, y-, y+.  Gravity points to -y (buoyancy +y, Eq. 5). */
+typedef struct {
+    int32_t kind[4];
+    double T_wall[4];
+} dmrt_bc;
+
+/* Model options; dmrt_opts_default() fills the paper's values (Sec. 4). */
+typedef struct {
+    double Ma;          /* Mach number fixing tau_nu and g beta DT (Sec. 4.3), 0.1      */
+    double J;           /* viscosity ratio nu_e/nu_l, Eq. (9), 1                        */
+    double lambda;      /* alpha_e/alpha_l, Eq. (9), 1                                  */
+    double alpha_ratio; /* alpha_l/alpha_s (Sec. 4.1), 1                                */
+    double sigma_s;     /* heat-capacity ratio of Eq. (7) in the solid, 1               */
+    double sigma_l;     /* ... in the liquid, 1                                         */
+    double T_s, T_l;    /* solidus / liquidus, Eqs. (41)-(42), -0.02 / 0.02             */
+    double T0;          /* Boussinesq reference temperature, Eq. (5), 0                 */
+    double T_init;      /* uniform initial temperature, 0                               */
+    double alpha_l;     /* liquid diffusivity (lattice) used when Ra == 0, 0.02         */
+    double varpi;       /* D2Q5 parameter of Eq. (34), -2                               */
+    double s_e, s_eps, s_q;   /* D2Q9 rates of Eq. (23): 1.1, 1.1, 1.2                  */
+    double zeta_e, zeta_nu;   /* D2Q5 rates zeta_3, zeta_4 of Eq. (37): 1.5, 1.5        */
+    double ergun_c;     /* constant of Eq. (6), 175                                     */
+    double fl_tol;      /* enthalpy iteration stops when |df_l| <= fl_tol, 1e-6         */
+    int32_t fl_maxit;   /* enthalpy iteration cap, 64                                   */
+    int32_t convective; /* vartheta of Eq. (34): 1 convection, 0 conduction, 1          */
+    int32_t check_every;/* >0: dmrt_step checks the state for NaN/Inf every this many
+                           steps and returns DMRT_ENONFINITE; 0: never                 */
+    int32_t graph_steps;/* >0: dmrt_step replays a captured HIP graph of this many
+                           steps (even); 0: plain launches, default 0                  */
+    void *stream;       /* hipStream_t for all work; NULL = null stream                 */
+} dmrt_opts;
+
+/* Lattice constants derived from the dimensionless inputs (Sec. 4.3). */
+typedef struct {
+    double H, tau_nu, nu_l, nu_e, alpha_l, alpha_s, gbeta, K_default;
+    double tau_T_liquid, tau_T_solid, csT2;
+} dmrt_derived;
+
+/* On-demand diagnostics of the current state. */
+typedef struct {
+    double mass;        /* sum of rho over flow-active cells (Eq. 24)           */
+    double enthalpy;    /* sum of sigma T + phi f_l / St (Eqs. 3, 40)           */
+    double liquid;      /* sum of f_l                                           */
+    double T_sum;       /* sum of T (Eq. 33)                                    */
+    double u_max;       /* max |u| over the lattice                             */
+    double front_mean;  /* mean over rows of the first f_l = 1/2 crossing from
+                           x = 0 (interpolated, measured from the x- wall)     */
+    double front_max;   /* max over rows of the same                            */
+    int64_t active;     /* cells with f_l > 0 (flow solved there, Sec. 4)       */
+    int64_t nonfinite;  /* NaN/Inf values found in the state                    */
+    int64_t step;       /* time steps taken                                     */
+} dmrt_diag_t;
+
+typedef struct dmrt dmrt_t;
+
+/* Fill o with the paper's defaults (Sec. 4). */
+void dmrt_opts_default(dmrt_opts *o);
+
+/* Host-only: lattice constants for (grid, Ra, Da, Pr, Ste, opts) following
+ * Sec. 4.3 (Ra > 0) or the given alpha_l (Ra == 0).  opts may be NULL.
+ * DMRT_EINVAL if a relaxation time is not above 1/2. No device work. */
+int dmrt_derive(const dmrt_grid *grid, double Ra, double Da, double Pr, double Ste,
+                const dmrt_opts *opts, dmrt_derived *out);
+
+/* Create a solver on the current HIP device and initialise it at rest with
+ * T = T_init, f_l = f_l(T_init) (Eq. 42), g = g^eq (Eq. 39), f = f^eq (Eq. 29).
+ *   eps  : porosity per cell, (0, 1]; required.
+ *   K    : permeability per cell at f_l = 1; NULL means Da * H^2 (Eq. 9).
+ *   Feps : inertial coefficient per cell at f_l = 1; NULL means the Ergun
+ *          relation 1.75 / sqrt(ergun_c eps^3) of Eq. (6).
+ *   Ra   : Rayleigh number; Ra == 0 means no buoyancy (conduction cases).
+ *   Da, Pr, Ste : Darcy, Prandtl and Stefan numbers of Eq. (9).
+ * opts may be NULL (defaults).  On success *out owns the device state. */
+int dmrt_create(const dmrt_grid *grid, const float *eps, const float *K, const float *Feps,
+                double Ra, double Da, double Pr, double Ste, const dmrt_bc *bc,
+                const dmrt_opts *opts, dmrt_t **out);
+
+/* Advance n >= 0 time steps (enqueued; returns before they finish unless a
+ * NaN check runs).  DMRT_ENONFINITE names the step in dmrt_last_error(). */
+int dmrt_step(dmrt_t *h, int64_t n);
+
+/* Fields at the current time: T (Eq. 33), u (Eq. 26; 0 in solid cells) and
+ * f_l.  Any pointer may be NULL; each takes nx*ny floats. */
+int dmrt_fields(dmrt_t *h, float *T, float *ux, float *uy, float *fl);
+
+/* Replace the state with the pre-collision populations f[9][ny][nx],
+ * g[5][ny][nx] and liquid fraction fl[ny][nx].  f may be NULL (rest
+ * equilibrium w_i rho0), g may be NULL (g^eq at T_init), fl may be NULL
+ * (f_l(T) of Eq. 42 with T = sum g).  The time counter is not changed. */
+int dmrt_set_state(dmrt_t *h, const float *f, const float *g, const float *fl);
+
+/* Post-collision populations of the current time step: fpost[9][ny][nx]
+ * (0 in solid cells) and gpost[5][ny][nx]; either may be NULL. */
+int dmrt_get_populations(dmrt_t *h, float *fpost, float *gpost);
+
+/* Reductions of the current state (see dmrt_diag_t). */
+int dmrt_diag(dmrt_t *h, dmrt_diag_t *out);
+
+/* Lattice constants the handle runs with. */
+int dmrt_get_derived(const dmrt_t *h, dmrt_derived *out);
+
+/* Enthalpy-iteration statistics of the last step taken with counting on:
+ * dmrt_step_counted(h, n) runs n steps and accumulates per-cell iteration
+ * counts; max_it and mean_it (over cells and steps) are returned. */
+int dmrt_step_counted(dmrt_t *h, int64_t n, int32_t *max_it, double *mean_it);
+
+/* Checkpoint: dmrt_state_bytes() bytes hold the complete state and the time
+ * counter; dmrt_save writes them to a host buffer of capacity cap
+ * (DMRT_ESIZE if smaller), dmrt_load restores them into a handle created
+ * with the same grid (DMRT_EINVAL otherwise). */
+int64_t dmrt_state_bytes(const dmrt_t *h);
+int dmrt_save(dmrt_t *h, void *buf, size_t cap);
+int dmrt_load(dmrt_t *h, const void *buf, size_t n);
+
+/* Time steps taken so far. */
+int64_t dmrt_time(const dmrt_t *h);
+
+/* Wait for the handle's stream. */
+int dmrt_sync(dmrt_t *h);
+
+/* Release the handle (NULL is ignored). */
+void dmrt_destroy(dmrt_t *h);
+
+/* Thread-local text of the last error ("" if none). */
+const char *dmrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMRT_H */

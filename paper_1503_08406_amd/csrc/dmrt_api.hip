@@ -1,0 +1,676 @@
+// C ABI of the double-MRT lattice Boltzmann phase-change solver: argument
+// checking, the dimensionless-to-lattice parameter mapping (Sec. 4.3 of
+// Liu & He, arXiv:1503.08406), device memory, launches, checkpoints.
+#include "../../include/dmrt.h"
+#include "dmrt_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using dmrtk::Geom;
+using dmrtk::Phys;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE, "%s: %s",  \
+                        #expr, hipGetErrorString(e_));                                      \
+    } while (0)
+
+constexpr uint64_t kMagic = 0x314d52544d444d44ull;  // checkpoint tag
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+}  // namespace
+
+struct dmrt {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    Geom G{};
+    Phys P{};
+    dmrt_derived D{};
+    double Ste = 1;
+    bool flow = false;
+    int cur = 0;  // buffer index holding the current state
+    int64_t t = 0;
+    int check_every = 0, graph_steps = 0;
+    char* base = nullptr;
+    float *f[2]{}, *g[2]{}, *fl[2]{};
+    float *ux = nullptr, *uy = nullptr, *eps = nullptr, *Ac = nullptr, *Bc = nullptr;
+    char* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int *it_sum = nullptr, *it_max = nullptr;
+    hipGraphExec_t graph[2]{};
+};
+
+namespace {
+
+int derive_impl(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
+                const dmrt_opts& o, dmrt_derived* d)
+{
+    if (!grid || !d) return fail(DMRT_EINVAL, "null argument");
+    if (grid->nx <= 0 || grid->ny <= 0) return fail(DMRT_EINVAL, "grid must be at least 1x1");
+    if (!(Ra >= 0) || !std::isfinite(Ra)) return fail(DMRT_EINVAL, "Ra must be >= 0");
+    if (!finite_pos(Pr) || !finite_pos(Ste)) return fail(DMRT_EINVAL, "Pr and Ste must be > 0");
+    if (!(Da > 0)) return fail(DMRT_EINVAL, "Da must be > 0");
+    if (!finite_pos(o.J) || !finite_pos(o.lambda) || !finite_pos(o.alpha_ratio) ||
+        !finite_pos(o.sigma_s) || !finite_pos(o.sigma_l))
+        return fail(DMRT_EINVAL, "J, lambda, alpha_ratio, sigma_s, sigma_l must be > 0");
+    if (!(o.varpi > -4 && o.varpi < 1)) return fail(DMRT_EINVAL, "varpi must lie in (-4, 1)");
+    d->H = grid->H > 0 ? grid->H : (double)grid->ny;
+    d->csT2 = (4.0 + o.varpi) / 10.0;
+    if (Ra > 0) {
+        if (!finite_pos(o.Ma)) return fail(DMRT_EINVAL, "Ma must be > 0");
+        // tau_nu from Ra, Pr, Ma and H; u_c = Ma c_s = sqrt(g beta DT H)
+        d->tau_nu = 0.5 + o.Ma * o.J * d->H * std::sqrt(3.0 * Pr) / std::sqrt(Ra);
+        d->nu_e = (d->tau_nu - 0.5) / 3.0;
+        d->nu_l = d->nu_e / o.J;
+        d->alpha_l = d->nu_l / Pr;
+        d->gbeta = o.Ma * o.Ma / (3.0 * d->H);
+    } else {
+        if (!finite_pos(o.alpha_l)) return fail(DMRT_EINVAL, "alpha_l must be > 0 when Ra == 0");
+        d->alpha_l = o.alpha_l;
+        d->nu_l = Pr * o.alpha_l;
+        d->nu_e = o.J * d->nu_l;
+        d->tau_nu = 0.5 + 3.0 * d->nu_e;
+        d->gbeta = 0.0;
+    }
+    d->alpha_s = d->alpha_l / o.alpha_ratio;
+    d->K_default = Da * d->H * d->H;
+    d->tau_T_liquid = 0.5 + o.lambda * d->alpha_l / (o.sigma_l * d->csT2);
+    d->tau_T_solid = 0.5 + o.lambda * d->alpha_s / (o.sigma_s * d->csT2);
+    if (!(d->tau_nu > 0.5) || !std::isfinite(d->tau_nu))
+        return fail(DMRT_EINVAL, "tau_nu = %g is not above 1/2", d->tau_nu);
+    if (!(d->tau_T_liquid > 0.5) || !(d->tau_T_solid > 0.5))
+        return fail(DMRT_EINVAL, "tau_T is not above 1/2");
+    return DMRT_OK;
+}
+
+int check_opts(const dmrt_opts& o)
+{
+    if (!(o.T_l > o.T_s)) return fail(DMRT_EINVAL, "T_l must exceed T_s");
+    if (!(o.fl_tol >= 0) || o.fl_maxit < 1) return fail(DMRT_EINVAL, "bad enthalpy iteration limits");
+    const double r[] = {o.s_e, o.s_eps, o.s_q, o.zeta_e, o.zeta_nu};
+    for (double v : r)
+        if (!(v > 0 && v < 2)) return fail(DMRT_EINVAL, "relaxation rates must lie in (0, 2)");
+    if (!finite_pos(o.ergun_c)) return fail(DMRT_EINVAL, "ergun_c must be > 0");
+    if (o.check_every < 0 || o.graph_steps < 0 || (o.graph_steps & 1))
+        return fail(DMRT_EINVAL, "check_every must be >= 0 and graph_steps even and >= 0");
+    return DMRT_OK;
+}
+
+int check_bc(const dmrt_bc* bc)
+{
+    if (!bc) return fail(DMRT_EINVAL, "null boundary spec");
+    for (int k = 0; k < 4; ++k)
+        if (bc->kind[k] < DMRT_PERIODIC || bc->kind[k] > DMRT_WALL_ADIABATIC)
+            return fail(DMRT_EINVAL, "unknown boundary kind on side %d", k);
+    if ((bc->kind[0] == DMRT_PERIODIC) != (bc->kind[1] == DMRT_PERIODIC) ||
+        (bc->kind[2] == DMRT_PERIODIC) != (bc->kind[3] == DMRT_PERIODIC))
+        return fail(DMRT_EINVAL, "periodic sides must come in pairs");
+    return DMRT_OK;
+}
+
+void fill_phys(dmrt* h, const dmrt_opts& o)
+{
+    Phys& P = h->P;
+    const dmrt_derived& d = h->D;
+    P.s_e = (float)o.s_e;
+    P.s_eps = (float)o.s_eps;
+    P.s_q = (float)o.s_q;
+    P.s_nu = (float)(1.0 / d.tau_nu);
+    P.zeta_e = (float)o.zeta_e;
+    P.zeta_nu = (float)o.zeta_nu;
+    P.w5_0 = (float)((1.0 - o.varpi) / 5.0);
+    P.w5_1 = (float)((4.0 + o.varpi) / 20.0);
+    P.varpi = (float)o.varpi;
+    P.csT2 = (float)d.csT2;
+    P.sig_s = (float)o.sigma_s;
+    P.dsig = (float)(o.sigma_l - o.sigma_s);
+    P.lam_as = (float)(o.lambda * d.alpha_s);
+    P.dlam = (float)(o.lambda * (d.alpha_l - d.alpha_s));
+    P.T_s = (float)o.T_s;
+    P.inv_St = (float)(1.0 / h->Ste);
+    P.inv_den = (float)(1.0 / (o.T_l - o.T_s + 1.0 / h->Ste));
+    P.inv_dTm = (float)(1.0 / (o.T_l - o.T_s));
+    P.gbeta = (float)d.gbeta;
+    P.T0 = (float)o.T0;
+    P.fl_tol = (float)o.fl_tol;
+    P.fl_maxit = o.fl_maxit;
+    P.conv = o.convective ? 1.0f : 0.0f;
+    P.zeta_uniform = (o.alpha_ratio == 1.0 && o.sigma_s == o.sigma_l) ? 1 : 0;
+    P.zeta_a = (float)(1.0 / d.tau_T_liquid);
+    P.T_init = (float)o.T_init;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int copy_in(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return DMRT_OK;
+}
+
+dmrtk::StepBufs bufs(dmrt* h, bool counted)
+{
+    dmrtk::StepBufs B;
+    const int a = h->cur, b = 1 - h->cur;
+    B.fin = h->f[a];
+    B.fout = h->f[b];
+    B.gin = h->g[a];
+    B.gout = h->g[b];
+    B.flin = h->fl[a];
+    B.flout = h->fl[b];
+    B.ux = h->ux;
+    B.uy = h->uy;
+    B.eps = h->eps;
+    B.Ac = h->Ac;
+    B.Bc = h->Bc;
+    B.it_sum = counted ? h->it_sum : nullptr;
+    B.it_max = counted ? h->it_max : nullptr;
+    return B;
+}
+
+int ensure_scratch(dmrt* h, size_t bytes)
+{
+    if (h->scratch_bytes >= bytes) return DMRT_OK;
+    if (h->scratch) HIPCHK(hipFree(h->scratch));
+    h->scratch = nullptr;
+    h->scratch_bytes = 0;
+    HIPCHK(hipMalloc(&h->scratch, bytes));
+    h->scratch_bytes = bytes;
+    return DMRT_OK;
+}
+
+// One plain step launch; flips the buffer index.
+int step_once(dmrt* h, bool counted)
+{
+    HIPCHK(dmrtk::launch_step(h->G, h->P, bufs(h, counted), h->flow, counted, h->stream));
+    h->cur = 1 - h->cur;
+    h->t += 1;
+    return DMRT_OK;
+}
+
+// Capture graph_steps launches starting from buffer parity p.
+int build_graph(dmrt* h, int p)
+{
+    const int save = h->cur;
+    const int64_t tsave = h->t;
+    h->cur = p;
+    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < h->graph_steps; ++k) {
+        hipError_t e = dmrtk::launch_step(h->G, h->P, bufs(h, false), h->flow, false, h->stream);
+        h->cur = 1 - h->cur;
+        if (e != hipSuccess) {
+            hipGraph_t gdrop;
+            (void)hipStreamEndCapture(h->stream, &gdrop);
+            if (gdrop) (void)hipGraphDestroy(gdrop);
+            h->cur = save;
+            return fail(DMRT_EDEVICE, "launch during capture: %s", hipGetErrorString(e));
+        }
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamEndCapture(h->stream, &graph));
+    hipError_t e = hipGraphInstantiate(&h->graph[p], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    h->cur = save;
+    h->t = tsave;
+    if (e != hipSuccess) return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return DMRT_OK;
+}
+
+int diag_impl(dmrt* h, dmrt_diag_t* out)
+{
+    const Geom& G = h->G;
+    const int nblk = dmrtk::NXCD * G.per_xcd;
+    const size_t pbytes = align256((size_t)nblk * dmrtk::DIAG_SLOTS * sizeof(double));
+    const size_t fbytes = (size_t)G.ny * sizeof(float);
+    int rc = ensure_scratch(h, pbytes + align256(fbytes));
+    if (rc) return rc;
+    double* part = (double*)h->scratch;
+    float* front = (float*)(h->scratch + pbytes);
+    int nb = 0;
+    const int a = h->cur;
+    HIPCHK(dmrtk::launch_diag(G, h->P, h->f[a], h->g[a], h->fl[a], h->ux, h->uy, h->eps, h->flow,
+                             part, &nb, h->stream));
+    HIPCHK(dmrtk::launch_front(G, h->fl[a], front, h->stream));
+    std::vector<double> hp((size_t)nb * dmrtk::DIAG_SLOTS);
+    std::vector<float> hf(G.ny);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipMemcpyAsync(hf.data(), front, fbytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double s[dmrtk::DIAG_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < dmrtk::DIAG_SLOTS; ++k) {
+            const double v = hp[(size_t)b * dmrtk::DIAG_SLOTS + k];
+            s[k] = (k == 4) ? std::fmax(s[k], v) : s[k] + v;
+        }
+    double fm = 0, fx = 0;
+    for (int r = 0; r < G.ny; ++r) {
+        fm += hf[r];
+        fx = std::fmax(fx, (double)hf[r]);
+    }
+    out->mass = s[0];
+    out->enthalpy = s[1];
+    out->liquid = s[2];
+    out->T_sum = s[3];
+    out->u_max = s[4];
+    out->active = (int64_t)llround(s[5]);
+    out->nonfinite = (int64_t)llround(s[6]);
+    out->front_mean = fm / G.ny;
+    out->front_max = fx;
+    out->step = h->t;
+    return DMRT_OK;
+}
+
+int check_finite(dmrt* h)
+{
+    dmrt_diag_t d;
+    int rc = diag_impl(h, &d);
+    if (rc) return rc;
+    if (d.nonfinite > 0 || !std::isfinite(d.enthalpy))
+        return fail(DMRT_ENONFINITE, "non-finite state detected at step %lld (%lld values)",
+                    (long long)h->t, (long long)d.nonfinite);
+    return DMRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dmrt_opts_default(dmrt_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->Ma = 0.1;
+    o->J = 1.0;
+    o->lambda = 1.0;
+    o->alpha_ratio = 1.0;
+    o->sigma_s = o->sigma_l = 1.0;
+    o->T_s = -0.02;
+    o->T_l = 0.02;
+    o->T0 = 0.0;
+    o->T_init = 0.0;
+    o->alpha_l = 0.02;
+    o->varpi = -2.0;
+    o->s_e = 1.1;
+    o->s_eps = 1.1;
+    o->s_q = 1.2;
+    o->zeta_e = 1.5;
+    o->zeta_nu = 1.5;
+    o->ergun_c = 175.0;
+    o->fl_tol = 1e-6;
+    o->fl_maxit = 64;
+    o->convective = 1;
+    o->check_every = 0;
+    o->graph_steps = 0;
+    o->stream = nullptr;
+}
+
+int dmrt_derive(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
+                const dmrt_opts* opts, dmrt_derived* out)
+{
+    dmrt_opts o;
+    if (opts) o = *opts; else dmrt_opts_default(&o);
+    return derive_impl(grid, Ra, Da, Pr, Ste, o, out);
+}
+
+int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const float* Feps,
+                double Ra, double Da, double Pr, double Ste, const dmrt_bc* bc,
+                const dmrt_opts* opts, dmrt_t** out)
+{
+    g_err.clear();
+    if (!out) return fail(DMRT_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!grid || !eps) return fail(DMRT_EINVAL, "grid and eps are required");
+    dmrt_opts o;
+    if (opts) o = *opts; else dmrt_opts_default(&o);
+    dmrt_derived d;
+    int rc = derive_impl(grid, Ra, Da, Pr, Ste, o, &d);
+    if (rc) return rc;
+    if ((rc = check_opts(o)) || (rc = check_bc(bc))) return rc;
+    const long long nx = grid->nx, ny = grid->ny;
+    const long long pitch = (nx + 63) / 64 * 64;
+    if (ny * pitch >= (1ll << 31)) return fail(DMRT_EINVAL, "lattice too large (%lld x %lld)", nx, ny);
+
+    dmrt* h = new (std::nothrow) dmrt;
+    if (!h) return fail(DMRT_ENOMEM, "host allocation");
+    h->D = d;
+    h->Ste = Ste;
+    h->check_every = o.check_every;
+    h->graph_steps = o.graph_steps;
+    h->stream = (hipStream_t)o.stream;
+    Geom& G = h->G;
+    G.nx = (int)nx;
+    G.ny = (int)ny;
+    G.pitch = (int)pitch;
+    G.plane = ny * pitch;
+    G.per_x = bc->kind[0] == DMRT_PERIODIC;
+    G.per_y = bc->kind[2] == DMRT_PERIODIC;
+    for (int k = 0; k < 4; ++k) {
+        G.wall_T[k] = bc->kind[k] == DMRT_WALL_T;
+        G.T_wall[k] = (float)bc->T_wall[k];
+    }
+    G.tiles_x = (int)((nx + dmrtk::TX - 1) / dmrtk::TX);
+    G.ntiles = G.tiles_x * (int)((ny + dmrtk::TY - 1) / dmrtk::TY);
+    G.per_xcd = (G.ntiles + dmrtk::NXCD - 1) / dmrtk::NXCD;
+    fill_phys(h, o);
+    h->flow = d.gbeta != 0.0;
+
+    auto bail = [&](int code) {
+        dmrt_destroy(h);
+        return code;
+    };
+    hipError_t e = hipGetDevice(&h->dev);
+    if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+
+    // Inputs: stage through host memory, validate, derive the drag coefficients.
+    const size_t ncell = (size_t)nx * ny;
+    std::vector<float> he(ncell), hk, hf;
+    if ((rc = copy_in(he.data(), eps, ncell * sizeof(float), h->stream))) return bail(rc);
+    if (K) {
+        hk.resize(ncell);
+        if ((rc = copy_in(hk.data(), K, ncell * sizeof(float), h->stream))) return bail(rc);
+    }
+    if (Feps) {
+        hf.resize(ncell);
+        if ((rc = copy_in(hf.data(), Feps, ncell * sizeof(float), h->stream))) return bail(rc);
+    }
+    const size_t pcell = (size_t)G.plane;
+    std::vector<float> pe(pcell, 1.0f), pa(pcell, 0.0f), pb(pcell, 0.0f);
+    for (long long y = 0; y < ny; ++y)
+        for (long long x = 0; x < nx; ++x) {
+            const size_t i = (size_t)(y * nx + x), j = (size_t)(y * pitch + x);
+            const double ep = he[i];
+            if (!(ep > 0.0 && ep <= 1.0))
+                return bail(fail(DMRT_EINVAL, "eps[%zu] = %g outside (0, 1]", i, ep));
+            const double k = K ? (double)hk[i] : d.K_default;
+            if (!(k > 0)) return bail(fail(DMRT_EINVAL, "K[%zu] = %g must be > 0", i, k));
+            const double cf = Feps ? (double)hf[i] : 1.75 / std::sqrt(o.ergun_c * ep * ep * ep);
+            if (!(cf >= 0) || !std::isfinite(cf))
+                return bail(fail(DMRT_EINVAL, "Feps[%zu] = %g must be finite and >= 0", i, cf));
+            pe[j] = (float)ep;
+            if (ep < 1.0) {  // eps = 1: clear fluid, no porous drag
+                pa[j] = (float)(ep * d.nu_l / (k * (1 - ep) * (1 - ep)));
+                pb[j] = (float)(ep * cf / (std::sqrt(k) * (1 - ep)));
+            }
+        }
+
+    // Device memory: one allocation, 256-byte aligned sub-arrays.
+    const size_t plane_b = align256(pcell * sizeof(float));
+    const size_t total = plane_b * (2 * 9 + 2 * 5 + 2 + 2 + 3);
+    e = hipMalloc(&h->base, total);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE,
+                         "hipMalloc(%zu): %s", total, hipGetErrorString(e)));
+    char* p = h->base;
+    auto take = [&](size_t planes) {
+        float* r = (float*)p;
+        p += planes * plane_b;
+        return r;
+    };
+    h->f[0] = take(9);
+    h->f[1] = take(9);
+    h->g[0] = take(5);
+    h->g[1] = take(5);
+    h->fl[0] = take(1);
+    h->fl[1] = take(1);
+    h->ux = take(1);
+    h->uy = take(1);
+    h->eps = take(1);
+    h->Ac = take(1);
+    h->Bc = take(1);
+    // Zero everything once: padding columns and inactive slots stay finite.
+    e = hipMemsetAsync(h->base, 0, total, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->eps, pe.data(), pcell * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->Ac, pa.data(), pcell * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->Bc, pb.data(), pcell * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "upload: %s", hipGetErrorString(e)));
+
+    // Initial state: uniform T_init at rest.
+    if ((rc = dmrt_set_state(h, nullptr, nullptr, nullptr))) return bail(rc);
+    *out = h;
+    return DMRT_OK;
+}
+
+int dmrt_set_state(dmrt_t* h, const float* f, const float* g, const float* fl)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(h->dev));
+    const Geom& G = h->G;
+    const size_t ncell = (size_t)G.nx * G.ny;
+    const size_t need = (f ? 9 : 0) * ncell + (g ? 5 : 0) * ncell + (fl ? 1 : 0) * ncell;
+    float *df = nullptr, *dg = nullptr, *dfl = nullptr;
+    if (need) {
+        int rc = ensure_scratch(h, need * sizeof(float));
+        if (rc) return rc;
+        float* s = (float*)h->scratch;
+        if (f) { df = s; s += 9 * ncell; HIPCHK(hipMemcpyAsync(df, f, 9 * ncell * 4, hipMemcpyDefault, h->stream)); }
+        if (g) { dg = s; s += 5 * ncell; HIPCHK(hipMemcpyAsync(dg, g, 5 * ncell * 4, hipMemcpyDefault, h->stream)); }
+        if (fl) { dfl = s; HIPCHK(hipMemcpyAsync(dfl, fl, ncell * 4, hipMemcpyDefault, h->stream)); }
+    }
+    if (f) h->flow = true;  // a given velocity field may move without gravity
+    const int a = h->cur;
+    HIPCHK(dmrtk::launch_load_state(G, h->P, df, dg, dfl, h->f[a], h->g[a], h->fl[a], h->ux, h->uy,
+                                   h->eps, h->Ac, h->Bc, h->flow, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_step(dmrt_t* h, int64_t n)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    if (n < 0) return fail(DMRT_EINVAL, "negative step count");
+    HIPCHK(hipSetDevice(h->dev));
+    int64_t since_check = 0;
+    while (n > 0) {
+        int64_t chunk = 1;
+        if (h->graph_steps > 0 && h->stream && n >= h->graph_steps &&
+            (h->check_every == 0 || h->check_every - since_check >= h->graph_steps)) {
+            const int p = h->cur;
+            if (!h->graph[p]) {
+                int rc = build_graph(h, p);
+                if (rc) return rc;
+            }
+            HIPCHK(hipGraphLaunch(h->graph[p], h->stream));
+            h->t += h->graph_steps;  // even count: buffer parity unchanged
+            chunk = h->graph_steps;
+        } else {
+            int rc = step_once(h, false);
+            if (rc) return rc;
+        }
+        n -= chunk;
+        since_check += chunk;
+        if (h->check_every > 0 && since_check >= h->check_every) {
+            since_check = 0;
+            int rc = check_finite(h);
+            if (rc) return rc;
+        }
+    }
+    return DMRT_OK;
+}
+
+int dmrt_step_counted(dmrt_t* h, int64_t n, int32_t* max_it, double* mean_it)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    if (n < 0) return fail(DMRT_EINVAL, "negative step count");
+    HIPCHK(hipSetDevice(h->dev));
+    const size_t pb = (size_t)h->G.plane * sizeof(int);
+    if (!h->it_sum) {
+        HIPCHK(hipMalloc(&h->it_sum, 2 * pb));
+        h->it_max = h->it_sum + h->G.plane;
+    }
+    HIPCHK(hipMemsetAsync(h->it_sum, 0, 2 * pb, h->stream));
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = step_once(h, true);
+        if (rc) return rc;
+    }
+    std::vector<int> hs(h->G.plane), hm(h->G.plane);
+    HIPCHK(hipMemcpyAsync(hs.data(), h->it_sum, pb, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(hm.data(), h->it_max, pb, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    long long tot = 0;
+    int mx = 0;
+    for (int y = 0; y < h->G.ny; ++y)
+        for (int x = 0; x < h->G.nx; ++x) {
+            const size_t j = (size_t)y * h->G.pitch + x;
+            tot += hs[j];
+            mx = hm[j] > mx ? hm[j] : mx;
+        }
+    if (max_it) *max_it = mx;
+    if (mean_it) *mean_it = n > 0 ? (double)tot / ((double)n * h->G.nx * h->G.ny) : 0.0;
+    return DMRT_OK;
+}
+
+int dmrt_fields(dmrt_t* h, float* T, float* ux, float* uy, float* fl)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(h->dev));
+    const Geom& G = h->G;
+    const size_t ncell = (size_t)G.nx * G.ny;
+    int rc = ensure_scratch(h, 4 * ncell * sizeof(float));
+    if (rc) return rc;
+    float* s = (float*)h->scratch;
+    const int a = h->cur;
+    HIPCHK(dmrtk::launch_fields(G, h->g[a], h->fl[a], h->ux, h->uy, h->flow, s, h->stream));
+    float* dst[4] = {T, ux, uy, fl};
+    for (int k = 0; k < 4; ++k)
+        if (dst[k]) HIPCHK(hipMemcpyAsync(dst[k], s + k * ncell, ncell * 4, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_get_populations(dmrt_t* h, float* fpost, float* gpost)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(h->dev));
+    const Geom& G = h->G;
+    const size_t ncell = (size_t)G.nx * G.ny;
+    int rc = ensure_scratch(h, 14 * ncell * sizeof(float));
+    if (rc) return rc;
+    float* s = (float*)h->scratch;
+    const int a = h->cur;
+    HIPCHK(dmrtk::launch_populations(G, h->f[a], h->g[a], h->fl[a], h->flow, s, s + 9 * ncell,
+                                    h->stream));
+    if (fpost) HIPCHK(hipMemcpyAsync(fpost, s, 9 * ncell * 4, hipMemcpyDefault, h->stream));
+    if (gpost) HIPCHK(hipMemcpyAsync(gpost, s + 9 * ncell, 5 * ncell * 4, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_diag(dmrt_t* h, dmrt_diag_t* out)
+{
+    if (!h || !out) return fail(DMRT_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(h->dev));
+    return diag_impl(h, out);
+}
+
+int dmrt_get_derived(const dmrt_t* h, dmrt_derived* out)
+{
+    if (!h || !out) return fail(DMRT_EINVAL, "null argument");
+    *out = h->D;
+    return DMRT_OK;
+}
+
+int64_t dmrt_state_bytes(const dmrt_t* h)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    return (int64_t)(64 + (size_t)h->G.plane * 17 * sizeof(float));
+}
+
+int dmrt_save(dmrt_t* h, void* buf, size_t cap)
+{
+    if (!h || !buf) return fail(DMRT_EINVAL, "null argument");
+    const int64_t need = dmrt_state_bytes(h);
+    if ((int64_t)cap < need) return fail(DMRT_ESIZE, "buffer holds %zu bytes, %lld needed", cap, (long long)need);
+    HIPCHK(hipSetDevice(h->dev));
+    uint64_t hdr[8] = {kMagic, (uint64_t)h->G.nx, (uint64_t)h->G.ny, (uint64_t)h->G.pitch,
+                       (uint64_t)h->t, (uint64_t)h->flow, 0, 0};
+    std::memcpy(buf, hdr, sizeof hdr);
+    char* p = (char*)buf + 64;
+    const size_t pb = (size_t)h->G.plane * sizeof(float);
+    const int a = h->cur;
+    HIPCHK(hipMemcpyAsync(p, h->f[a], 9 * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + 9 * pb, h->g[a], 5 * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + 14 * pb, h->fl[a], pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + 15 * pb, h->ux, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + 16 * pb, h->uy, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_load(dmrt_t* h, const void* buf, size_t n)
+{
+    if (!h || !buf) return fail(DMRT_EINVAL, "null argument");
+    if ((int64_t)n < dmrt_state_bytes(h)) return fail(DMRT_EINVAL, "checkpoint too short");
+    uint64_t hdr[8];
+    std::memcpy(hdr, buf, sizeof hdr);
+    if (hdr[0] != kMagic || hdr[1] != (uint64_t)h->G.nx || hdr[2] != (uint64_t)h->G.ny ||
+        hdr[3] != (uint64_t)h->G.pitch)
+        return fail(DMRT_EINVAL, "checkpoint does not match this lattice");
+    HIPCHK(hipSetDevice(h->dev));
+    const char* p = (const char*)buf + 64;
+    const size_t pb = (size_t)h->G.plane * sizeof(float);
+    const int a = h->cur;
+    HIPCHK(hipMemcpyAsync(h->f[a], p, 9 * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->g[a], p + 9 * pb, 5 * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->fl[a], p + 14 * pb, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->ux, p + 15 * pb, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->uy, p + 16 * pb, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->t = (int64_t)hdr[4];
+    h->flow = h->flow || hdr[5] != 0;
+    return DMRT_OK;
+}
+
+int64_t dmrt_time(const dmrt_t* h) { return h ? h->t : fail(DMRT_EINVAL, "null handle"); }
+
+int dmrt_sync(dmrt_t* h)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(h->dev));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+void dmrt_destroy(dmrt_t* h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->dev);
+    if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
+    for (auto& g : h->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (h->base) (void)hipFree(h->base);
+    if (h->scratch) (void)hipFree(h->scratch);
+    if (h->it_sum) (void)hipFree(h->it_sum);
+    delete h;
+}
+
+const char* dmrt_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

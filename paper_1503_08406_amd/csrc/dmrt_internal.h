@@ -1,0 +1,91 @@
+// Internal types shared by the HIP kernels and the C ABI of the double-MRT
+// lattice Boltzmann solver (Liu & He, arXiv:1503.08406).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dmrtk {
+
+// Launch geometry of the fused step: one lattice node per lane, a tile is a
+// 64-wide row segment (one wavefront) times TY rows.
+constexpr int TX = 64;
+constexpr int TY = 4;
+constexpr int NXCD = 8;  // MI355X: 8 accelerator dies, each with its own L2
+
+// Uniform model constants of one run, in the form the kernels use them.
+struct Phys {
+    float s_e, s_eps, s_q, s_nu;  // D2Q9 rates, Eq. (23)
+    float zeta_e, zeta_nu;        // D2Q5 rates zeta_3, zeta_4, Eq. (37)
+    float w5_0, w5_1;             // D2Q5 weights below Eq. (39)
+    float varpi, csT2;            // Eq. (34) parameter, c_sT^2
+    float sig_s, dsig;            // sigma(f_l) = sig_s + f_l dsig
+    float lam_as, dlam;           // lambda alpha_e(f_l) = lam_as + f_l dlam
+    float T_s, inv_St, inv_den;   // inv_den = 1 / (T_l - T_s + 1/St)
+    float inv_dTm;                // 1 / (T_l - T_s)
+    float gbeta, T0;              // buoyancy, Eq. (5)
+    float fl_tol;
+    int fl_maxit;
+    float conv;                   // vartheta of Eq. (34)
+    int zeta_uniform;             // 1 when zeta_alpha does not depend on f_l
+    float zeta_a;                 // that uniform zeta_alpha
+    float T_init;
+};
+
+// Lattice geometry and boundary description.
+struct Geom {
+    int nx, ny, pitch;  // pitch: row stride in elements (multiple of 64)
+    long long plane;    // elements per population plane = ny * pitch
+    int per_x, per_y;   // periodic axes
+    int wall_T[4];      // side x-, x+, y-, y+: 1 fixed temperature, 0 adiabatic
+    float T_wall[4];
+    int tiles_x, ntiles, per_xcd;
+};
+
+// Device buffers of one step (deviation populations for f).
+struct StepBufs {
+    const float* __restrict__ fin;
+    float* __restrict__ fout;
+    const float* __restrict__ gin;
+    float* __restrict__ gout;
+    const float* __restrict__ flin;
+    float* __restrict__ flout;
+    float* __restrict__ ux;
+    float* __restrict__ uy;
+    const float* __restrict__ eps;
+    const float* __restrict__ Ac;  // phi nu_l / (K (1-phi)^2): Darcy coefficient
+    const float* __restrict__ Bc;  // phi F_eps / (sqrt(K) (1-phi)): Forchheimer
+    int* __restrict__ it_sum;      // enthalpy-iteration counters (counted mode)
+    int* __restrict__ it_max;
+};
+
+hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flow,
+                       bool counted, hipStream_t s);
+
+// Load a pre-collision state (planar, row stride nx; any of f/g/fl may be
+// null) and store its post-collision populations into the current buffers.
+hipError_t launch_load_state(const Geom& G, const Phys& P, const float* f_pre,
+                             const float* g_pre, const float* fl_pre, float* fcur,
+                             float* gcur, float* flcur, float* ux, float* uy,
+                             const float* eps, const float* Ac, const float* Bc,
+                             bool flow, hipStream_t s);
+
+// T, ux, uy, f_l into out[4][ny][nx].
+hipError_t launch_fields(const Geom& G, const float* gcur, const float* flcur,
+                         const float* ux, const float* uy, bool flow, float* out,
+                         hipStream_t s);
+
+// Full post-collision populations into fpost[9][ny][nx], gpost[5][ny][nx].
+hipError_t launch_populations(const Geom& G, const float* fcur, const float* gcur,
+                              const float* flcur, bool flow, float* fpost, float* gpost,
+                              hipStream_t s);
+
+constexpr int DIAG_SLOTS = 8;  // doubles per block partial
+hipError_t launch_diag(const Geom& G, const Phys& P, const float* fcur, const float* gcur,
+                       const float* flcur, const float* ux, const float* uy,
+                       const float* eps, bool flow, double* partials, int* nblocks,
+                       hipStream_t s);
+hipError_t launch_front(const Geom& G, const float* flcur, float* front, hipStream_t s);
+
+}  // namespace dmrtk

@@ -1,0 +1,260 @@
+"""Python binding of the HIP double-MRT solver (libdmrt.so, C ABI in
+include/dmrt.h).  Argument marshalling only: every step of the method runs in
+the library's kernels.  PyTorch supplies the HIP stream (and, when asked,
+device tensors for outputs).  There is no CPU fallback: if the library is
+missing, importing the binding raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmrt.so")
+
+DMRT_OK, DMRT_EINVAL, DMRT_ENOMEM, DMRT_EDEVICE, DMRT_ENONFINITE, DMRT_ESIZE = 0, -1, -2, -3, -4, -5
+PERIODIC, WALL_T, WALL_ADIABATIC = 0, 1, 2
+
+
+class DmrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("dmrt error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("H", C.c_double)]
+
+
+class BC(C.Structure):
+    _fields_ = [("kind", C.c_int32 * 4), ("T_wall", C.c_double * 4)]
+
+
+class Opts(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("Ma", "J", "lambda_", "alpha_ratio", "sigma_s", "sigma_l", "T_s", "T_l", "T0",
+                 "T_init", "alpha_l", "varpi", "s_e", "s_eps", "s_q", "zeta_e", "zeta_nu",
+                 "ergun_c", "fl_tol")] + \
+              [("fl_maxit", C.c_int32), ("convective", C.c_int32), ("check_every", C.c_int32),
+               ("graph_steps", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Derived(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("H", "tau_nu", "nu_l", "nu_e", "alpha_l", "alpha_s", "gbeta", "K_default",
+                 "tau_T_liquid", "tau_T_solid", "csT2")]
+
+
+class Diag(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("mass", "enthalpy", "liquid", "T_sum", "u_max", "front_mean", "front_max")] + \
+              [("active", C.c_int64), ("nonfinite", C.c_int64), ("step", C.c_int64)]
+
+
+def _hip_runtimes():
+    """Distinct HIP runtime files mapped into this process."""
+    try:
+        with open("/proc/self/maps") as fh:
+            return sorted({ln.split()[-1] for ln in fh if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdmrt.so not built at %s (run __graft_entry__.build())" % LIB_PATH)
+    # PyTorch's HIP runtime must be loaded first: the library then binds to it
+    # (same soname) instead of mapping a second runtime into the process.
+    import torch  # noqa: F401
+    import torch.cuda  # noqa: F401
+    lib = C.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError("two HIP runtimes are mapped into the process: %s" % rts)
+    P, FP, VP = C.c_void_p, C.POINTER(C.c_float), C.c_void_p
+    sig = {
+        "dmrt_opts_default": (None, [C.POINTER(Opts)]),
+        "dmrt_derive": (C.c_int, [C.POINTER(Grid), C.c_double, C.c_double, C.c_double, C.c_double,
+                                  C.POINTER(Opts), C.POINTER(Derived)]),
+        "dmrt_create": (C.c_int, [C.POINTER(Grid), VP, VP, VP, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.POINTER(BC), C.POINTER(Opts), C.POINTER(P)]),
+        "dmrt_step": (C.c_int, [P, C.c_int64]),
+        "dmrt_fields": (C.c_int, [P, VP, VP, VP, VP]),
+        "dmrt_set_state": (C.c_int, [P, VP, VP, VP]),
+        "dmrt_get_populations": (C.c_int, [P, VP, VP]),
+        "dmrt_diag": (C.c_int, [P, C.POINTER(Diag)]),
+        "dmrt_get_derived": (C.c_int, [P, C.POINTER(Derived)]),
+        "dmrt_step_counted": (C.c_int, [P, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "dmrt_state_bytes": (C.c_int64, [P]),
+        "dmrt_save": (C.c_int, [P, VP, C.c_size_t]),
+        "dmrt_load": (C.c_int, [P, VP, C.c_size_t]),
+        "dmrt_time": (C.c_int64, [P]),
+        "dmrt_sync": (C.c_int, [P]),
+        "dmrt_destroy": (None, [P]),
+        "dmrt_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != DMRT_OK:
+        raise DmrtError(rc, _lib.dmrt_last_error().decode())
+    return rc
+
+
+def default_opts():
+    o = Opts()
+    _lib.dmrt_opts_default(C.byref(o))
+    return o
+
+
+def make_opts(**kw):
+    o = default_opts()
+    for k, v in kw.items():
+        if k == "lambda":
+            k = "lambda_"
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def derive(nx, ny, Ra, Da, Pr, Ste, H=0.0, **opts):
+    g = Grid(nx, ny, H)
+    d = Derived()
+    _check(_lib.dmrt_derive(C.byref(g), Ra, Da, Pr, Ste, C.byref(make_opts(**opts)), C.byref(d)))
+    return {n: getattr(d, n) for n, _ in Derived._fields_}
+
+
+def _ptr(a):
+    """Pointer of a float32 host array (numpy) or device tensor (torch)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        assert a.dtype.__str__() == "torch.float32" and a.is_contiguous()
+        return C.c_void_p(a.data_ptr())
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Solver:
+    """One lattice on one GPU.  `case` is a workload dict of
+    paper_1503_08406_amd.workloads; keyword arguments override its options."""
+
+    def __init__(self, case, stream=None, **over):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the dmrt solver needs a ROCm GPU")
+        self.torch = torch
+        self.nx, self.ny = case["nx"], case["ny"]
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        opts = dict(case["opts"])
+        opts.update(over)
+        o = make_opts(**opts)
+        o.stream = C.c_void_p(self.stream.cuda_stream)
+        g = Grid(self.nx, self.ny, case["H"])
+        bc = BC()
+        for k in range(4):
+            bc.kind[k] = case["bc_kind"][k]
+            bc.T_wall[k] = case["T_wall"][k]
+        self._keep = [np.ascontiguousarray(case["eps"], dtype=np.float32)]
+        K = case["K"]
+        F = case["Feps"]
+        self._keep += [None if K is None else np.ascontiguousarray(K, dtype=np.float32),
+                       None if F is None else np.ascontiguousarray(F, dtype=np.float32)]
+        h = C.c_void_p()
+        _check(_lib.dmrt_create(C.byref(g), _ptr(self._keep[0]), _ptr(self._keep[1]),
+                                _ptr(self._keep[2]), case["Ra"], case["Da"], case["Pr"],
+                                case["Ste"], C.byref(bc), C.byref(o), C.byref(h)))
+        self._h = h
+        d = Derived()
+        _check(_lib.dmrt_get_derived(self._h, C.byref(d)))
+        self.derived = {n: getattr(d, n) for n, _ in Derived._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dmrt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def time(self):
+        return _lib.dmrt_time(self._h)
+
+    def step(self, n=1):
+        _check(_lib.dmrt_step(self._h, int(n)))
+
+    def step_counted(self, n):
+        mx = C.c_int32()
+        mean = C.c_double()
+        _check(_lib.dmrt_step_counted(self._h, int(n), C.byref(mx), C.byref(mean)))
+        return mx.value, mean.value
+
+    def sync(self):
+        _check(_lib.dmrt_sync(self._h))
+
+    def fields(self):
+        shape = (self.ny, self.nx)
+        out = {k: np.zeros(shape, np.float32) for k in ("T", "ux", "uy", "fl")}
+        _check(_lib.dmrt_fields(self._h, _ptr(out["T"]), _ptr(out["ux"]), _ptr(out["uy"]),
+                                _ptr(out["fl"])))
+        return out
+
+    def fields_device(self):
+        """Fields written straight into device tensors."""
+        t = self.torch
+        out = {k: t.empty((self.ny, self.nx), dtype=t.float32, device="cuda")
+               for k in ("T", "ux", "uy", "fl")}
+        t.cuda.current_stream().synchronize()
+        _check(_lib.dmrt_fields(self._h, _ptr(out["T"]), _ptr(out["ux"]), _ptr(out["uy"]),
+                                _ptr(out["fl"])))
+        return out
+
+    def set_state(self, f=None, g=None, fl=None):
+        conv = lambda a, q: None if a is None else np.ascontiguousarray(
+            np.asarray(a, dtype=np.float32).reshape((q, self.ny, self.nx) if q else (self.ny, self.nx)))
+        f, g, fl = conv(f, 9), conv(g, 5), conv(fl, 0)
+        _check(_lib.dmrt_set_state(self._h, _ptr(f), _ptr(g), _ptr(fl)))
+
+    def populations(self):
+        fp = np.zeros((9, self.ny, self.nx), np.float32)
+        gp = np.zeros((5, self.ny, self.nx), np.float32)
+        _check(_lib.dmrt_get_populations(self._h, _ptr(fp), _ptr(gp)))
+        return fp, gp
+
+    def diag(self):
+        d = Diag()
+        _check(_lib.dmrt_diag(self._h, C.byref(d)))
+        return {n: getattr(d, n) for n, _ in Diag._fields_}
+
+    def save(self):
+        n = _lib.dmrt_state_bytes(self._h)
+        if n < 0:
+            _check(int(n))
+        buf = np.zeros(n, np.uint8)
+        _check(_lib.dmrt_save(self._h, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
+        return buf
+
+    def load(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(_lib.dmrt_load(self._h, buf.ctypes.data_as(C.c_void_p), buf.nbytes))

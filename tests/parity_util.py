@@ -1,0 +1,40 @@
+"""Helpers shared by the GPU parity tests: build the HIP solver and the FP64
+oracle on the same workload and compare them with the tolerances of the
+spec contract (T: relative L-inf 1e-4; u: relative L-inf 1e-3;
+f_l: L-inf 1e-3; front: 0.5 lattice units)."""
+import numpy as np
+
+from conftest import front_rows, oracle_from_case
+
+TOL_T, TOL_U, TOL_FL, TOL_FRONT = 1e-4, 1e-3, 1e-3, 0.5
+
+
+def pair(case, gpu_over=None, **over):
+    """(HIP solver, oracle) on the same workload; gpu_over holds options only
+    the HIP side takes (launch options, its FP32 enthalpy tolerance)."""
+    from paper_1503_08406_amd.dmrt import Solver
+    g = dict(over)
+    g.update(gpu_over or {})
+    return Solver(case, **g), oracle_from_case(case, **over)
+
+
+def field_errors(fg, fo):
+    """Errors of GPU fields fg against oracle fields fo (dicts)."""
+    Tmax = max(np.abs(fo["T"]).max(), 1e-30)
+    umax = max(np.abs(fo["ux"]).max(), np.abs(fo["uy"]).max(), 1e-30)
+    du = max(np.abs(fg["ux"] - fo["ux"]).max(), np.abs(fg["uy"] - fo["uy"]).max())
+    return dict(T=np.abs(fg["T"] - fo["T"]).max() / Tmax,
+                u=du / umax, u_abs=du, umax=umax,
+                fl=np.abs(fg["fl"] - fo["fl"]).max(),
+                front=np.abs(front_rows(fg["fl"]) - front_rows(fo["fl"])).max())
+
+
+def assert_fields_close(fg, fo, tol_T=TOL_T, tol_u=TOL_U, tol_fl=TOL_FL, tol_front=TOL_FRONT,
+                        u_floor=0.0, label=""):
+    e = field_errors(fg, fo)
+    msg = "%s %s" % (label, {k: float("%.3g" % v) for k, v in e.items()})
+    assert e["T"] <= tol_T, msg
+    assert e["u"] <= tol_u or e["u_abs"] <= u_floor, msg
+    assert e["fl"] <= tol_fl, msg
+    assert e["front"] <= tol_front, msg
+    return e

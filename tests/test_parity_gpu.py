@@ -1,0 +1,245 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.  Tolerances are the spec contract (T relative
+L-inf <= 1e-4, u relative L-inf <= 1e-3, f_l L-inf <= 1e-3, front within 0.5
+lattice units); single steps on random states are checked population by
+population at FP32 round-off level."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import front_rows, oracle_from_case
+from parity_util import assert_fields_close, field_errors, pair
+from paper_1503_08406_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L(oracle_mod):
+    return oracle_mod.lattice()
+
+
+# boundary layouts: (kinds x-, x+, y-, y+), wall temperatures
+BCS = {
+    "periodic": ([0, 0, 0, 0], [0, 0, 0, 0]),
+    "walls_x": ([1, 2, 0, 0], [0.9, 0, 0, 0]),
+    "box": ([1, 1, 2, 2], [0.9, 0.1, 0, 0]),
+    "mixed": ([2, 1, 1, 2], [0, 0.05, 0.7, 0]),
+}
+
+
+def _random_case(nx, ny, bc, Ra=2e5, **kw):
+    kinds, tw = BCS[bc]
+    opts = dict(T_init=0.4, T_s=0.38, T_l=0.42, convective=1)
+    opts.update(kw)
+    return W.make_case("rand", nx, ny, kinds, tw, Ra=Ra, Da=2e-3, Pr=1.0, Ste=0.8, eps=0.45,
+                       H=64, **opts)
+
+
+@pytest.mark.parametrize("bc", list(BCS))
+def test_load_state_post_collision_matches_oracle(L, bc):
+    """Set an arbitrary pre-collision state on both sides; the post-collision
+    populations (Eqs. 20, 35) agree at FP32 round-off."""
+    nx, ny = 70, 37  # two 64-wide tiles with a ragged tail, ragged in y
+    case = _random_case(nx, ny, bc)
+    f, g, fl = W.random_state(nx, ny, 5, L["w9"], L["w5"])
+    _say("load_state", bc)
+    s, o = pair(case)
+    s.set_state(f, g, fl)
+    o.set_state(f.astype(float), g.astype(float), fl.astype(float))
+    fp, gp = s.populations()
+    fo, go = o.post_collision()
+    assert np.abs(fp - fo).max() < 2e-7
+    assert np.abs(gp - go).max() < 2e-7
+    Fg, Fo = s.fields(), o.fields()
+    assert np.abs(Fg["ux"] - Fo["ux"]).max() < 1e-7 and np.abs(Fg["uy"] - Fo["uy"]).max() < 1e-7
+    assert np.array_equal(Fg["fl"], fl)
+
+
+@pytest.mark.parametrize("bc", list(BCS))
+def test_steps_on_random_state_match_oracle(L, bc):
+    """One to twelve full steps from a random mixed solid/mushy/liquid state:
+    pull-streaming, wall and interface extrapolation, enthalpy update, mask
+    changes and both collisions agree population by population."""
+    nx, ny = 70, 37
+    case = _random_case(nx, ny, bc)
+    f, g, fl = W.random_state(nx, ny, 9, L["w9"], L["w5"])
+    # the FP32 enthalpy iteration stops at |df_l| <= 1e-7 (contraction about
+    # 0.5 here), so f_l carries ~1e-7 per step on top of FP32 round-off
+    s, o = pair(case, gpu_over=dict(fl_tol=1e-7))
+    s.set_state(f, g, fl)
+    o.set_state(f.astype(float), g.astype(float), fl.astype(float))
+    for n in (1, 1, 2, 8):
+        _say("random steps", bc, n)
+        s.step(n)
+        o.step(n)
+        fp, gp = s.populations()
+        fo, go = o.post_collision()
+        Fg, Fo = s.fields(), o.fields()
+        act_g, act_o = Fg["fl"] > 0, Fo["fl"] > 0
+        assert np.array_equal(act_g, act_o), "flow masks differ"
+        assert np.abs(Fg["fl"] - Fo["fl"]).max() < 2e-6
+        assert np.abs(gp - go).max() < 2e-6
+        assert np.abs(fp - fo).max() < 2e-6
+        assert np.abs(Fg["ux"] - Fo["ux"]).max() < 2e-6
+    assert o.time == s.time == 12
+
+
+def test_conduction_slab_full_size():
+    """Sec. 4.1 workload at its stated size: 256x4, porosity 0.5, Ste 1,
+    5000 steps; GPU vs oracle, and the front vs the Neumann solution."""
+    case = W.conduction_slab()
+    s, o = pair(case)
+    _say("conduction slab 5000 steps")
+    s.step(5000)
+    o.step(5000)
+    Fg, Fo = s.fields(), o.fields()
+    assert_fields_close(Fg, Fo, u_floor=1e-12, label="slab")
+    assert np.abs(Fg["ux"]).max() == 0 and np.abs(Fg["uy"]).max() == 0
+    xm = 2 * 0.417942 * math.sqrt(0.02 * 5000)  # Eqs. (43), (46) with phi L_a
+    assert np.abs(front_rows(Fg["fl"]) - xm).max() < 0.5
+    d = s.diag()
+    assert abs(d["front_mean"] - front_rows(Fo["fl"]).mean()) < 0.5
+
+
+def test_corner_reduced_matches_oracle():
+    """Sec. 4.2 setting at 96x96 for 3000 steps: elementwise parity and the
+    exact x <-> y symmetry of the GPU result."""
+    case = W.corner(n=96, steps=3000)
+    s, o = pair(case)
+    _say("corner 96^2 3000 steps")
+    s.step(3000)
+    o.step(3000)
+    Fg, Fo = s.fields(), o.fields()
+    assert_fields_close(Fg, Fo, u_floor=1e-12, label="corner")
+    assert np.abs(Fg["T"] - Fg["T"].T).max() < 1e-5
+
+
+@pytest.mark.parametrize("nx,ny,Ra,steps", [(96, 80, 1e5, 3000), (130, 67, 5e5, 2000)])
+def test_convective_cavity_matches_oracle(nx, ny, Ra, steps):
+    """Sec. 4.3 setting (hot left, cold right, adiabatic top/bottom, porous
+    matrix with log-normal K) on ragged small lattices: melting with natural
+    convection and a moving interface."""
+    case = W.cavity(nx=nx, ny=ny, steps=steps, Ra=Ra, Da=5e-3, Ste=0.5, seed=3, T_init=0.2)
+    s, o = pair(case)
+    _say("cavity", nx, ny, Ra, steps)
+    for k in range(4):
+        s.step(steps // 4)
+        o.step(steps // 4)
+        Fg, Fo = s.fields(), o.fields()
+        e = assert_fields_close(Fg, Fo, label="cavity step %d" % s.time)
+    assert e["umax"] > 1e-4 and (Fo["fl"] > 0).sum() > 100
+
+
+def test_degenerate_lattices():
+    """Edge cases: a single periodic node, a one-node-wide channel between
+    walls, a lattice that stays fully solid and one that is fully liquid."""
+    cases = [
+        W.make_case("one", 1, 1, [0] * 4, [0] * 4, Ra=1e4, Da=1e-2, Pr=1, Ste=1, eps=0.5, H=8,
+                    T_init=0.5, T_s=0.1, T_l=0.2),
+        W.make_case("line", 1, 9, [1, 1, 2, 2], [1.0, 0.0, 0, 0], Ra=1e4, Da=1e-2, Pr=1, Ste=1,
+                    eps=0.5, H=8, T_init=0.5, T_s=0.1, T_l=0.2),
+        W.make_case("solid", 67, 5, [1, 2, 0, 0], [-0.5, 0, 0, 0], Ra=1e4, Da=1e-2, Pr=1, Ste=1,
+                    eps=0.5, H=8, T_init=-1.0, T_s=0.1, T_l=0.2),
+        W.make_case("liquid", 65, 9, [1, 1, 2, 2], [1.0, 0.5, 0, 0], Ra=1e5, Da=1e-2, Pr=1,
+                    Ste=1, eps=0.9, H=9, T_init=0.8, T_s=0.1, T_l=0.2),
+    ]
+    for case in cases:
+        _say("degenerate", case["name"])
+        s, o = pair(case)
+        s.step(300)
+        o.step(300)
+        assert_fields_close(s.fields(), o.fields(), u_floor=1e-9, label=case["name"])
+
+
+def test_conservation_on_gpu(L):
+    """Periodic box: total mass (all liquid) and total enthalpy (with melting)
+    are conserved by the FP32 kernels to round-off drift."""
+    nx, ny = 64, 48
+    case = W.periodic_box(nx, ny, 0.4, T_s=-1.02, T_l=-0.98)
+    from paper_1503_08406_amd.dmrt import Solver
+    s = Solver(case)
+    f, g, fl = W.random_state(nx, ny, 2, L["w9"], L["w5"])
+    s.set_state(f, g, np.ones_like(fl))
+    d0 = s.diag()
+    s.step(2000)
+    d1 = s.diag()
+    assert abs(d1["mass"] - d0["mass"]) / d0["mass"] < 1e-6
+    case = W.periodic_box(nx, ny, 0.4, T_s=0.38, T_l=0.42, Ste=0.7)
+    s = Solver(case)
+    s.set_state(f, g, fl)
+    d0 = s.diag()
+    s.step(2000)
+    d1 = s.diag()
+    assert abs(d1["enthalpy"] - d0["enthalpy"]) / abs(d0["enthalpy"]) < 1e-5
+    assert d1["nonfinite"] == 0
+
+
+def test_save_load_resume_is_bit_identical():
+    """Checkpoint, continue, restore and continue again: identical fields."""
+    case = W.cavity(nx=80, ny=64, Ra=2e5, Da=5e-3, Ste=0.5, T_init=0.2)
+    from paper_1503_08406_amd.dmrt import Solver
+    s = Solver(case)
+    s.step(500)
+    buf = s.save()
+    s.step(300)
+    a = s.fields()
+    s2 = Solver(case)
+    s2.load(buf)
+    assert s2.time == 500
+    s2.step(300)
+    b = s2.fields()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_graph_replay_equals_plain_launches():
+    """Steps replayed from a captured HIP graph give the same bits as plain
+    launches, across several replays with eager work in between."""
+    case = W.cavity(nx=100, ny=60, Ra=2e5, Da=5e-3, Ste=0.5, T_init=0.2)
+    from paper_1503_08406_amd.dmrt import Solver
+    s1 = Solver(case)
+    s2 = Solver(case, graph_steps=8)
+    for _ in range(4):
+        s1.step(40)
+        s2.step(40)
+        s2.diag()
+        a, b = s1.fields(), s2.fields()
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    s2.step(13)  # odd remainder mixes graph and plain launches
+    s1.step(13)
+    assert np.array_equal(s1.fields()["T"], s2.fields()["T"])
+
+
+def test_nonfinite_state_is_reported(L):
+    """A NaN planted in the state (from the host) makes dmrt_step return
+    DMRT_ENONFINITE when checking is on."""
+    from paper_1503_08406_amd.dmrt import DmrtError, DMRT_ENONFINITE, Solver
+    case = W.cavity(nx=64, ny=32, Ra=2e5, Da=5e-3, Ste=0.5, T_init=0.2)
+    s = Solver(case, check_every=10)
+    f, g, fl = W.random_state(64, 32, 1, L["w9"], L["w5"])
+    g[0, 5, 7] = np.nan
+    s.set_state(f, g, fl)
+    with pytest.raises(DmrtError) as ei:
+        s.step(30)
+    assert ei.value.code == DMRT_ENONFINITE
+    assert "step" in str(ei.value)
+
+
+def test_enthalpy_iteration_counts():
+    """The counted step reports per-cell iteration statistics: bulk cells
+    converge in one or two iterations, front cells take more."""
+    case = W.cavity(nx=96, ny=64, Ra=2e5, Da=5e-3, Ste=0.5, T_init=0.2)
+    from paper_1503_08406_amd.dmrt import Solver
+    s = Solver(case)
+    s.step(500)
+    mx, mean = s.step_counted(20)
+    assert 1 <= mean < 3 and mx > 3
