@@ -2,7 +2,7 @@
 // checking, the dimensionless-to-lattice parameter mapping (Sec. 4.3 of
 // Liu & He, arXiv:1503.08406), device memory, launches, checkpoints.
 #include "../../include/dmrt.h"
-#include "dmrt_internal.h"
+#include "dmrt_device.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -118,6 +118,8 @@ int check_opts(const dmrt_opts& o)
     if (!finite_pos(o.ergun_c)) return fail(DMRT_EINVAL, "ergun_c must be > 0");
     if (o.check_every < 0 || o.graph_steps < 0 || (o.graph_steps & 1))
         return fail(DMRT_EINVAL, "check_every must be >= 0 and graph_steps even and >= 0");
+    if (o.block_rows != 0 && o.block_rows != 4 && o.block_rows != 8 && o.block_rows != 16)
+        return fail(DMRT_EINVAL, "block_rows must be 0, 4, 8 or 16");
     return DMRT_OK;
 }
 
@@ -147,8 +149,10 @@ void fill_phys(dmrt* h, const dmrt_opts& o)
     P.w5_1 = (float)((4.0 + o.varpi) / 20.0);
     P.varpi = (float)o.varpi;
     P.csT2 = (float)d.csT2;
+    P.inv_csT2 = (float)(1.0 / d.csT2);
     P.sig_s = (float)o.sigma_s;
     P.dsig = (float)(o.sigma_l - o.sigma_s);
+    P.isig_s = (float)(1.0 / o.sigma_s);
     P.lam_as = (float)(o.lambda * d.alpha_s);
     P.dlam = (float)(o.lambda * (d.alpha_l - d.alpha_s));
     P.T_s = (float)o.T_s;
@@ -245,7 +249,7 @@ int build_graph(dmrt* h, int p)
 int diag_impl(dmrt* h, dmrt_diag_t* out)
 {
     const Geom& G = h->G;
-    const int nblk = dmrtk::NXCD * G.per_xcd;
+    const int nblk = dmrtk::tile_blocks(G, dmrtk::TY);
     const size_t pbytes = align256((size_t)nblk * dmrtk::DIAG_SLOTS * sizeof(double));
     const size_t fbytes = (size_t)G.ny * sizeof(float);
     int rc = ensure_scratch(h, pbytes + align256(fbytes));
@@ -328,6 +332,7 @@ void dmrt_opts_default(dmrt_opts* o)
     o->convective = 1;
     o->check_every = 0;
     o->graph_steps = 0;
+    o->block_rows = 0;
     o->stream = nullptr;
 }
 
@@ -375,9 +380,9 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
         G.wall_T[k] = bc->kind[k] == DMRT_WALL_T;
         G.T_wall[k] = (float)bc->T_wall[k];
     }
-    G.tiles_x = (int)((nx + dmrtk::TX - 1) / dmrtk::TX);
-    G.ntiles = G.tiles_x * (int)((ny + dmrtk::TY - 1) / dmrtk::TY);
-    G.per_xcd = (G.ntiles + dmrtk::NXCD - 1) / dmrtk::NXCD;
+    G.block_rows = o.block_rows ? o.block_rows : 4;
+    // 32-bit buffer addressing while the largest array (9 planes) fits 4 GB
+    G.wide = (uint64_t)G.plane * 4 * 9 >= (1ull << 32) ? 1 : 0;
     fill_phys(h, o);
     h->flow = d.gbeta != 0.0;
 

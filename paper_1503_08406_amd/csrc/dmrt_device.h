@@ -1,0 +1,182 @@
+// Device-side building blocks of the double-MRT lattice Boltzmann kernels
+// (Liu & He, arXiv:1503.08406): tile decoding, memory access policies and
+// the per-node collision arithmetic shared by the step and state kernels.
+#pragma once
+
+#include "dmrt_internal.h"
+
+namespace dmrtk {
+
+constexpr float W9_0 = 4.0f / 9.0f, W9_1 = 1.0f / 9.0f, W9_2 = 1.0f / 36.0f;
+
+__device__ __forceinline__ float w9(int i) { return i == 0 ? W9_0 : (i <= 4 ? W9_1 : W9_2); }
+
+// Hardware reciprocal and square root (1 ulp); the arithmetic of a node does
+// not need correctly rounded division.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Tile of this block for a launch of 64 x TYB threads.  Blocks are handed to
+// the 8 dies round-robin, so block b takes tile (b % 8)*per_xcd + b/8: each
+// die sweeps one contiguous band of rows and the pull-stencil halo rows stay
+// in that die's L2.
+template <int TYB>
+__device__ __forceinline__ bool tile_coords(const Geom& G, int& x, int& y)
+{
+    const int tiles_x = (G.nx + TX - 1) / TX;
+    const int ntiles = tiles_x * ((G.ny + TYB - 1) / TYB);
+    const int per_xcd = (ntiles + NXCD - 1) / NXCD;
+    const int b = blockIdx.x;
+    const int tile = (b % NXCD) * per_xcd + b / NXCD;
+    if (tile >= ntiles) return false;
+    x = (tile % tiles_x) * TX + (int)threadIdx.x;
+    y = (tile / tiles_x) * TYB + (int)threadIdx.y;
+    return x < G.nx && y < G.ny;
+}
+
+inline int tile_blocks(const Geom& G, int TYB)
+{
+    const int tiles_x = (G.nx + TX - 1) / TX;
+    const int ntiles = tiles_x * ((G.ny + TYB - 1) / TYB);
+    return NXCD * ((ntiles + NXCD - 1) / NXCD);
+}
+
+// Access to an array of float planes.  BufIO uses a buffer resource with a
+// 32-bit byte offset per node (VGPR) and a 32-bit plane offset (SGPR): one
+// instruction per access, range-checked by the hardware.  PtrIO is the
+// 64-bit pointer form for arrays larger than 4 GB.
+struct BufIO {
+    using off_t = uint32_t;
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BufIO(const float* p, uint64_t nbytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(uint32_t)nbytes, 0x00020000))
+    {
+    }
+    __device__ __forceinline__ float ld(off_t o, off_t plane_off) const
+    {
+        // the b32 buffer intrinsics move raw 32-bit words: bit-cast, never convert
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, plane_off, 0));
+    }
+    __device__ __forceinline__ void st(off_t o, off_t plane_off, float v) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, plane_off, 0);
+    }
+};
+
+struct PtrIO {
+    using off_t = uint64_t;
+    char* p;
+    __device__ __forceinline__ PtrIO(const float* q, uint64_t) : p((char*)q) {}
+    __device__ __forceinline__ float ld(off_t o, off_t plane_off) const
+    {
+        return *(const float*)(p + plane_off + o);
+    }
+    __device__ __forceinline__ void st(off_t o, off_t plane_off, float v) const
+    {
+        *(float*)(p + plane_off + o) = v;
+    }
+};
+
+// Velocity closure and D2Q9 MRT collision of one node, on the deviations
+// d_i = f_i - w_i rho0 (rho0 = 1).  Eqs. (24)-(28) give u; the total force
+// of Eq. (4) follows from Eq. (25) as F = 2 (u - j) (an exact identity); the
+// porous drag of Eq. (6) is taken in varphi = phi f_l; Eq. (20) is applied
+// as f+ = f - M^-1 Delta with Delta = Lambda (m - m^eq) - (I - Lambda/2) S
+// (Eqs. 19, 22, 23).  Ac = phi nu_l / (K (1-phi)^2), Bc = phi F_eps /
+// (sqrt(K) (1-phi)) are the drag coefficients at f_l = 1.
+__device__ __forceinline__ void flow_collide(float (&d)[9], float fl1, float eps, float Ac,
+                                             float Bc, float T1, const Phys& P, float& ux,
+                                             float& uy)
+{
+    const float sa = (d[1] + d[2]) + (d[3] + d[4]);
+    const float sd = (d[5] + d[6]) + (d[7] + d[8]);
+    const float rho_d = d[0] + sa + sd;
+    const float dx13 = d[1] - d[3], dy24 = d[2] - d[4];
+    const float a58 = d[5] - d[7], b68 = d[6] - d[8];  // e_x: a58 - b68, e_y: a58 + b68
+    const float jx = dx13 + (a58 - b68);
+    const float jy = dy24 + (a58 + b68);
+    const float phi = eps * fl1;
+    const float vy = jy + 0.5f * phi * (P.gbeta * (T1 - P.T0));  // Eq. (27)
+    const float vx = jx;
+    // Eq. (28) with K_e = K f_l^3 ((1-phi)/(1-varphi))^2 and
+    // C_e = F_eps f_l^(-3/2), multiplied through by f_l^2 so that no term
+    // overflows as f_l -> 0.
+    const float w2 = fl1 * fl1, om = 1.0f - phi;
+    const float l0 = 0.5f * (w2 + 0.5f * Ac * om * om);
+    const float l1 = 0.5f * Bc * om;
+    const float vm = fsqrt(vx * vx + vy * vy);
+    const float den = l0 + fsqrt(l0 * l0 + l1 * w2 * vm);  // Eq. (26) times f_l^2
+    const float sc = den > 0.0f ? w2 * frcp(den) : 0.0f;
+    ux = vx * sc;
+    uy = vy * sc;
+    const float Fx = 2.0f * (ux - jx), Fy = 2.0f * (uy - jy);
+
+    const float iphi = frcp(phi);
+    const float m1 = 2.0f * sd - sa - 4.0f * d[0];
+    const float m2 = sd - 2.0f * sa + 4.0f * d[0];
+    const float m4 = (a58 - b68) - 2.0f * dx13;
+    const float m6 = (a58 + b68) - 2.0f * dy24;
+    const float m7 = (d[1] + d[3]) - (d[2] + d[4]);
+    const float m8 = (d[5] + d[7]) - (d[6] + d[8]);
+    // equilibrium moments (Eq. 19) minus their rest values, forcing (Eq. 22)
+    const float uxi = ux * iphi, uyi = uy * iphi;
+    const float q = 3.0f * (ux * uxi + uy * uyi);
+    const float S1 = 6.0f * (uxi * Fx + uyi * Fy);
+    const float S7 = 2.0f * (uxi * Fx - uyi * Fy);
+    const float S8 = uxi * Fy + uyi * Fx;
+    const float D1 = P.s_e * (m1 + 2.0f * rho_d - q) - (1.0f - 0.5f * P.s_e) * S1;
+    const float D2 = P.s_eps * (m2 - rho_d + q) + (1.0f - 0.5f * P.s_eps) * S1;
+    const float D4 = P.s_q * (m4 + ux) + (1.0f - 0.5f * P.s_q) * Fx;
+    const float D6 = P.s_q * (m6 + uy) + (1.0f - 0.5f * P.s_q) * Fy;
+    const float D7 = P.s_nu * (m7 - (ux * uxi - uy * uyi)) - (1.0f - 0.5f * P.s_nu) * S7;
+    const float D8 = P.s_nu * (m8 - ux * uyi) - (1.0f - 0.5f * P.s_nu) * S8;
+    // conserved moments: Delta_3 = -F_x, Delta_5 = -F_y for any s_3 = s_5.
+    // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+    const float a = D1 * (1.0f / 36.0f), b = D2 * (1.0f / 36.0f);
+    const float ca = -a - 2.0f * b, cd = 2.0f * a + b;
+    const float X1 = (-Fx - D4) * (1.0f / 6.0f), Y1 = (-Fy - D6) * (1.0f / 6.0f);
+    const float X2 = D4 * (1.0f / 12.0f) - Fx * (1.0f / 6.0f);
+    const float Y2 = D6 * (1.0f / 12.0f) - Fy * (1.0f / 6.0f);
+    const float Pq = 0.25f * D7, Qq = 0.25f * D8;
+    d[0] -= 4.0f * (b - a);
+    d[1] -= ca + X1 + Pq;
+    d[2] -= ca + Y1 - Pq;
+    d[3] -= ca - X1 + Pq;
+    d[4] -= ca - Y1 - Pq;
+    d[5] -= cd + X2 + Y2 + Qq;
+    d[6] -= cd - X2 + Y2 - Qq;
+    d[7] -= cd - X2 - Y2 + Qq;
+    d[8] -= cd + X2 - Y2 - Qq;
+}
+
+// zeta_alpha = 1/tau_T(f_l) with tau_T = 1/2 + alpha_e(f_l)/(sigma c_sT^2).
+__device__ __forceinline__ float zeta_alpha(const Phys& P, float fl, float isig)
+{
+    if (P.zeta_uniform) return P.zeta_a;
+    return frcp(0.5f + (P.lam_as + fl * P.dlam) * isig * P.inv_csT2);
+}
+
+// D2Q5 MRT collision (Eqs. 32, 34, 35, 37) with temperature T1 and
+// 1/sigma = isig.
+__device__ __forceinline__ void thermal_collide(float (&g)[5], float fl1, float isig, float T1,
+                                                float ux, float uy, const Phys& P)
+{
+    const float n1 = g[1] - g[3], n2 = g[2] - g[4];
+    const float s13 = g[1] + g[3], s24 = g[2] + g[4];
+    const float n3 = (s13 + s24) - 4.0f * g[0];
+    const float n4 = s13 - s24;
+    const float za = zeta_alpha(P, fl1, isig);
+    const float ct = P.conv * T1 * isig;
+    const float D1 = za * (n1 - ct * ux), D2 = za * (n2 - ct * uy);
+    const float D3 = P.zeta_e * (n3 - P.varpi * T1), D4 = P.zeta_nu * n4;
+    // N^-1 = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4)
+    const float c3 = 0.05f * D3, c4 = 0.25f * D4;
+    const float h1 = 0.5f * D1, h2 = 0.5f * D2;
+    g[0] += 0.2f * D3;
+    g[1] -= h1 + c3 + c4;
+    g[2] -= h2 + c3 - c4;
+    g[3] -= c3 + c4 - h1;
+    g[4] -= c3 - c4 - h2;
+}
+
+}  // namespace dmrtk

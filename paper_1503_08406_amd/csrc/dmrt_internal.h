@@ -11,7 +11,7 @@ namespace dmrtk {
 // Launch geometry of the fused step: one lattice node per lane, a tile is a
 // 64-wide row segment (one wavefront) times TY rows.
 constexpr int TX = 64;
-constexpr int TY = 4;
+constexpr int TY = 4;   // block rows of the auxiliary kernels
 constexpr int NXCD = 8;  // MI355X: 8 accelerator dies, each with its own L2
 
 // Uniform model constants of one run, in the form the kernels use them.
@@ -19,8 +19,8 @@ struct Phys {
     float s_e, s_eps, s_q, s_nu;  // D2Q9 rates, Eq. (23)
     float zeta_e, zeta_nu;        // D2Q5 rates zeta_3, zeta_4, Eq. (37)
     float w5_0, w5_1;             // D2Q5 weights below Eq. (39)
-    float varpi, csT2;            // Eq. (34) parameter, c_sT^2
-    float sig_s, dsig;            // sigma(f_l) = sig_s + f_l dsig
+    float varpi, csT2, inv_csT2;  // Eq. (34) parameter, c_sT^2, 1/c_sT^2
+    float sig_s, dsig, isig_s;    // sigma(f_l) = sig_s + f_l dsig, 1/sig_s
     float lam_as, dlam;           // lambda alpha_e(f_l) = lam_as + f_l dlam
     float T_s, inv_St, inv_den;   // inv_den = 1 / (T_l - T_s + 1/St)
     float inv_dTm;                // 1 / (T_l - T_s)
@@ -40,7 +40,8 @@ struct Geom {
     int per_x, per_y;   // periodic axes
     int wall_T[4];      // side x-, x+, y-, y+: 1 fixed temperature, 0 adiabatic
     float T_wall[4];
-    int tiles_x, ntiles, per_xcd;
+    int block_rows;     // rows of a step-kernel block (4, 8 or 16)
+    int wide;           // 1: 64-bit addressing (arrays beyond a 4 GB window)
 };
 
 // Device buffers of one step (deviation populations for f).

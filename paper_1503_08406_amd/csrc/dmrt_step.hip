@@ -1,0 +1,236 @@
+// The fused time step of the double-MRT lattice Boltzmann phase-change model
+// (Liu & He, arXiv:1503.08406) for gfx950.  One launch = one time step; one
+// lane owns one node.
+//
+// Per node, with start-of-step state (post-collision populations f+, g+ of
+// step k, liquid fraction f_l^k, the node's own velocity u^k):
+//   1. pull g_i(x) = g+_i(x - e_i) (Eq. 36); a wall source gives
+//      g_i^eq(T_w, 0) + g+_i(x) - g_i^eq(T^k(x), u^k(x)).
+//   2. iterate the enthalpy update (Eqs. 38, 40-42) to f_l^{k+1}, T^{k+1} and
+//      add the latent source w~_i S~_0 to g (Eq. 38 through N^-1).
+//   3. where f_l^{k+1} > 0: pull f_i(x) = f+_i(x - e_i) from liquid sources;
+//      a wall or solid source gives f_i^eq(rho, 0) + f+_i(x) - f_i^eq(rho,
+//      u^k; varphi^k) (rho cancels); a node that just melted restarts at
+//      rest; then the closure and the MRT collision with forcing.
+//   4. D2Q5 MRT collision, store f+, g+, f_l^{k+1}, u^{k+1}.
+//
+// Memory phases: f_l^k first; then every pull of the node in one batch (g,
+// the neighbour liquid fractions, and f from all lattice neighbours when the
+// node was liquid, discarding the values of solid sources afterwards); the
+// node's own post-collision values are read only where an extrapolation
+// needs them.
+#include "dmrt_device.h"
+
+namespace dmrtk {
+namespace {
+
+template <class IO, bool FLOW, bool COUNT, int TYB>
+__global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
+{
+    using off_t = typename IO::off_t;
+    int x, y;
+    if (!tile_coords<TYB>(G, x, y)) return;
+    const off_t pb = (off_t)G.plane * 4u;  // bytes per population plane
+    const IO fin(B.fin, 9 * (uint64_t)pb), fout(B.fout, 9 * (uint64_t)pb);
+    const IO gin(B.gin, 5 * (uint64_t)pb), gout(B.gout, 5 * (uint64_t)pb);
+    const IO flin(B.flin, pb), flout(B.flout, pb);
+    const IO uv(B.ux, 2 * (uint64_t)pb);    // ux plane, then uy plane
+    const IO stat(B.eps, 3 * (uint64_t)pb);  // eps, Ac, Bc planes
+
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    bool wxm = false, wxp = false, wym = false, wyp = false;
+    if (xm < 0) { if (G.per_x) xm += G.nx; else wxm = true; }
+    if (xp >= G.nx) { if (G.per_x) xp -= G.nx; else wxp = true; }
+    if (ym < 0) { if (G.per_y) ym += G.ny; else wym = true; }
+    if (yp >= G.ny) { if (G.per_y) yp -= G.ny; else wyp = true; }
+    const off_t pitch = (off_t)G.pitch;
+    const off_t r0 = (off_t)y * pitch, rm = (off_t)ym * pitch, rp = (off_t)yp * pitch;
+    const off_t o = (r0 + (off_t)x) * 4u;
+    const bool w5 = wxm | wym, w6 = wxp | wym, w7 = wxp | wyp, w8 = wxm | wyp;
+    const bool wall = wxm | wxp | wym | wyp;
+    // byte offsets of the sources x - e_i; a source behind a wall is pointed
+    // at the node itself (always in bounds) and its value is replaced below,
+    // so every pull is an unconditional load
+    const off_t o1 = wxm ? o : (r0 + (off_t)xm) * 4u, o3 = wxp ? o : (r0 + (off_t)xp) * 4u;
+    const off_t o2 = wym ? o : (rm + (off_t)x) * 4u, o4 = wyp ? o : (rp + (off_t)x) * 4u;
+    const off_t o5 = w5 ? o : (rm + (off_t)xm) * 4u, o6 = w6 ? o : (rm + (off_t)xp) * 4u;
+    const off_t o7 = w7 ? o : (rp + (off_t)xp) * 4u, o8 = w8 ? o : (rp + (off_t)xm) * 4u;
+
+    const float flk = flin.ld(o, 0);
+    const bool act0 = FLOW && flk > 0.0f;
+
+    // ---- all pulls of this node, issued together
+    const float eps = stat.ld(o, 0);
+    float g[5];
+    g[0] = gin.ld(o, 0);
+    g[1] = gin.ld(o1, pb);
+    g[2] = gin.ld(o2, 2 * pb);
+    g[3] = gin.ld(o3, 3 * pb);
+    g[4] = gin.ld(o4, 4 * pb);
+    float d[9];
+    bool nee_f = false;
+    unsigned liq = 0;  // bit i set: source of direction i is a liquid node
+    float Ac = 0.0f, Bc = 0.0f;
+    if (act0) {
+        const float n1 = flin.ld(o1, 0), n2 = flin.ld(o2, 0), n3 = flin.ld(o3, 0);
+        const float n4 = flin.ld(o4, 0), n5 = flin.ld(o5, 0), n6 = flin.ld(o6, 0);
+        const float n7 = flin.ld(o7, 0), n8 = flin.ld(o8, 0);
+        d[0] = fin.ld(o, 0);
+        d[1] = fin.ld(o1, pb);
+        d[2] = fin.ld(o2, 2 * pb);
+        d[3] = fin.ld(o3, 3 * pb);
+        d[4] = fin.ld(o4, 4 * pb);
+        d[5] = fin.ld(o5, 5 * pb);
+        d[6] = fin.ld(o6, 6 * pb);
+        d[7] = fin.ld(o7, 7 * pb);
+        d[8] = fin.ld(o8, 8 * pb);
+        Ac = stat.ld(o, pb);
+        Bc = stat.ld(o, 2 * pb);
+        liq = (unsigned)(!wxm & (n1 > 0.0f)) << 1 | (unsigned)(!wym & (n2 > 0.0f)) << 2 |
+              (unsigned)(!wxp & (n3 > 0.0f)) << 3 | (unsigned)(!wyp & (n4 > 0.0f)) << 4 |
+              (unsigned)(!w5 & (n5 > 0.0f)) << 5 | (unsigned)(!w6 & (n6 > 0.0f)) << 6 |
+              (unsigned)(!w7 & (n7 > 0.0f)) << 7 | (unsigned)(!w8 & (n8 > 0.0f)) << 8;
+        nee_f = liq != 0x1FEu;
+    }
+    float uxk = 0.0f, uyk = 0.0f;
+    if (act0 & (wall | nee_f)) {
+        uxk = uv.ld(o, 0);
+        uyk = uv.ld(o, pb);
+    }
+
+    // ---- wall sources of g (start-of-step values of this node)
+    if (wall) {
+        const float q1 = gin.ld(o, pb), q2 = gin.ld(o, 2 * pb);
+        const float q3 = gin.ld(o, 3 * pb), q4 = gin.ld(o, 4 * pb);
+        const float Tk = g[0] + ((q1 + q3) + (q2 + q4));
+        const float cu = frcp((P.sig_s + flk * P.dsig) * P.csT2);
+        const float wTk = P.w5_1 * Tk;
+        if (wxm) g[1] = P.w5_1 * (G.wall_T[0] ? G.T_wall[0] : Tk) + q1 - wTk * (1.0f + uxk * cu);
+        if (wym) g[2] = P.w5_1 * (G.wall_T[2] ? G.T_wall[2] : Tk) + q2 - wTk * (1.0f + uyk * cu);
+        if (wxp) g[3] = P.w5_1 * (G.wall_T[1] ? G.T_wall[1] : Tk) + q3 - wTk * (1.0f - uxk * cu);
+        if (wyp) g[4] = P.w5_1 * (G.wall_T[3] ? G.T_wall[3] : Tk) + q4 - wTk * (1.0f - uyk * cu);
+    }
+
+    // ---- iterated enthalpy update (Eqs. 38, 40-42) at the receiving node;
+    // the wavefront loops until every lane has converged.
+    const float Tstar = g[0] + ((g[1] + g[3]) + (g[2] + g[4]));
+    const float alat = eps * P.inv_St;  // phi L_a / c_p
+    float f = flk;
+    int it = 0;
+    if (P.dsig == 0.0f) {
+        const float a = alat * P.isig_s;
+        for (;;) {
+            ++it;
+            const float En = (Tstar - a * (f - flk)) + f * P.inv_St;
+            const float fn = fminf(fmaxf((En - P.T_s) * P.inv_den, 0.0f), 1.0f);
+            const bool done = fabsf(fn - f) <= P.fl_tol || it >= P.fl_maxit;
+            f = fn;
+            if (done) break;
+        }
+    } else {
+        for (;;) {
+            ++it;
+            const float T = Tstar - alat * (f - flk) * frcp(P.sig_s + f * P.dsig);
+            const float fn = fminf(fmaxf((T + f * P.inv_St - P.T_s) * P.inv_den, 0.0f), 1.0f);
+            const bool done = fabsf(fn - f) <= P.fl_tol || it >= P.fl_maxit;
+            f = fn;
+            if (done) break;
+        }
+    }
+    const float fl1 = f;
+    const float isig1 = P.dsig == 0.0f ? P.isig_s : frcp(P.sig_s + fl1 * P.dsig);
+    const float dT = -alat * (fl1 - flk) * isig1;  // S~_0 (Eq. 38)
+    const float T1 = Tstar + dT;
+    g[0] += P.w5_0 * dT;
+    g[1] += P.w5_1 * dT;
+    g[2] += P.w5_1 * dT;
+    g[3] += P.w5_1 * dT;
+    g[4] += P.w5_1 * dT;
+    if (COUNT) {
+        const size_t ci = (size_t)y * G.pitch + x;
+        B.it_sum[ci] += it;
+        if (it > B.it_max[ci]) B.it_max[ci] = it;
+    }
+
+    // ---- flow where f_l^{k+1} > 0 (Sec. 4)
+    float ux = 0.0f, uy = 0.0f;
+    if (FLOW && fl1 > 0.0f) {
+        if (act0) {
+            if (nee_f) {
+                const float iph = frcp(eps * flk);
+                const float uu = 1.5f * (uxk * uxk + uyk * uyk) * iph;
+#define DMRT_NEE(I, N, EU, W)                                                          \
+    if (!(liq & (1u << I))) {                                                         \
+        const float eu = (EU);                                                        \
+        d[I] = fin.ld(o, I * pb) - (W) * (3.0f * eu + 4.5f * eu * eu * iph - uu);     \
+    }
+                DMRT_NEE(1, n1, uxk, W9_1)
+                DMRT_NEE(2, n2, uyk, W9_1)
+                DMRT_NEE(3, n3, -uxk, W9_1)
+                DMRT_NEE(4, n4, -uyk, W9_1)
+                DMRT_NEE(5, n5, uxk + uyk, W9_2)
+                DMRT_NEE(6, n6, uyk - uxk, W9_2)
+                DMRT_NEE(7, n7, -uxk - uyk, W9_2)
+                DMRT_NEE(8, n8, uxk - uyk, W9_2)
+#undef DMRT_NEE
+            }
+        } else {
+            // the node melted in this step: restart at rest, f_i = w_i rho0
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] = 0.0f;
+            Ac = stat.ld(o, pb);
+            Bc = stat.ld(o, 2 * pb);
+        }
+        flow_collide(d, fl1, eps, Ac, Bc, T1, P, ux, uy);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fout.st(o, (off_t)i * pb, d[i]);
+        uv.st(o, 0, ux);
+        uv.st(o, pb, uy);
+    }
+
+    thermal_collide(g, fl1, isig1, T1, ux, uy, P);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) gout.st(o, (off_t)i * pb, g[i]);
+    flout.st(o, 0, fl1);
+}
+
+template <class IO, bool FLOW, bool COUNT>
+hipError_t launch_rows(const Geom& G, const Phys& P, const StepBufs& B, hipStream_t s)
+{
+    const int rows = G.block_rows;
+    const dim3 grd(tile_blocks(G, rows));
+    switch (rows) {
+    case 8:
+        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 8>), grd, dim3(TX, 8), 0, s, G, P, B);
+        break;
+    case 16:
+        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 16>), grd, dim3(TX, 16), 0, s, G, P, B);
+        break;
+    default:
+        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 4>), grd, dim3(TX, 4), 0, s, G, P, B);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <class IO>
+hipError_t launch_io(const Geom& G, const Phys& P, const StepBufs& B, bool flow, bool counted,
+                     hipStream_t s)
+{
+    if (flow)
+        return counted ? launch_rows<IO, true, true>(G, P, B, s)
+                       : launch_rows<IO, true, false>(G, P, B, s);
+    return counted ? launch_rows<IO, false, true>(G, P, B, s)
+                   : launch_rows<IO, false, false>(G, P, B, s);
+}
+
+}  // namespace
+
+hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flow, bool counted,
+                       hipStream_t s)
+{
+    if (G.wide) return launch_io<PtrIO>(G, P, B, flow, counted, s);
+    return launch_io<BufIO>(G, P, B, flow, counted, s);
+}
+
+}  // namespace dmrtk
