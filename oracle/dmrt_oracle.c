@@ -18,8 +18,10 @@
  *   - Eq. (6) is read in varphi = phi*f_l; the per-cell inputs K and F_eps are
  *     the values at f_l = 1, so K_e = K (varphi/phi)^3 ((1-phi)/(1-varphi))^2
  *     and C_e = F_eps (phi/varphi)^(3/2).  phi = 1 means clear fluid (no drag).
- *   - The flow is solved where f_l > 0; a cell that becomes active restarts
- *     at f_i = w_i rho0, a cell that becomes solid drops its populations.
+ *   - The flow is solved where f_l > 0.  A cell that becomes liquid restarts
+ *     at rest at the mean density of its liquid neighbours (rho0 if none), so
+ *     melting launches no pressure pulse; a cell that becomes solid drops its
+ *     populations.
  *   - Boundaries: link-wise non-equilibrium extrapolation at the receiving
  *     node.  A wall lies one lattice unit outside the first node.  A missing
  *     population gets equilibrium(wall values) + (own post-collision value -
@@ -715,13 +717,33 @@ static void one_step(orc_sim *s)
         s->flnew[c] = fln;
     }
 
-    /* Step 7: flow mask update. */
+    /* Step 7: flow mask update.  A node that became liquid starts at rest,
+     * f_i = w_i rho_bar, with rho_bar the mean start-of-step density of its
+     * liquid lattice neighbours (rho0 if it has none); a node that became
+     * solid drops its populations. */
 #pragma omp parallel for num_threads(nt) schedule(static)
-    for (long c = 0; c < nc; ++c) {
-        int was = s->fl[c] > 0, now = s->flnew[c] > 0;
-        for (int i = 0; i < Q9; ++i) {
-            if (now && !was) s->fnew[c * Q9 + i] = s->L9.w[i] * RHO0;
-            else if (!now) s->fnew[c * Q9 + i] = 0;
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            long c = (long)y * nx + x;
+            int was = s->fl[c] > 0, now = s->flnew[c] > 0;
+            if (now && !was) {
+                double rsum = 0;
+                int cnt = 0;
+                for (int i = 1; i < Q9; ++i) {
+                    int sx, sy, side;
+                    if (source_node(s, x, y, s->L9.ex[i], s->L9.ey[i], &sx, &sy, &side)) {
+                        long sc = (long)sy * nx + sx;
+                        if (s->chi[sc]) {
+                            rsum += s->rho[sc];
+                            ++cnt;
+                        }
+                    }
+                }
+                double rbar = cnt ? rsum / cnt : RHO0;
+                for (int i = 0; i < Q9; ++i) s->fnew[c * Q9 + i] = s->L9.w[i] * rbar;
+            } else if (!now) {
+                for (int i = 0; i < Q9; ++i) s->fnew[c * Q9 + i] = 0;
+            }
         }
     }
 

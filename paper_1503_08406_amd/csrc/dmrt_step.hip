@@ -11,7 +11,8 @@
 //   3. where f_l^{k+1} > 0: pull f_i(x) = f+_i(x - e_i) from liquid sources;
 //      a wall or solid source gives f_i^eq(rho, 0) + f+_i(x) - f_i^eq(rho,
 //      u^k; varphi^k) (rho cancels); a node that just melted restarts at
-//      rest; then the closure and the MRT collision with forcing.
+//      rest at the mean density of its liquid neighbours; then the closure
+//      and the MRT collision with forcing.
 //   4. D2Q5 MRT collision, store f+, g+, f_l^{k+1}, u^{k+1}.
 //
 // Memory phases: f_l^k first; then every pull of the node in one batch (g,
@@ -175,9 +176,27 @@ __global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
 #undef DMRT_NEE
             }
         } else {
-            // the node melted in this step: restart at rest, f_i = w_i rho0
+            // the node melted in this step: restart at rest at the mean
+            // start-of-step density of its liquid neighbours (rho0 if none),
+            // f_i = w_i rho_bar; rho - 1 of a neighbour is the sum of its
+            // stored post-collision deviations (collision conserves mass)
+            const off_t on[8] = {o1, o2, o3, o4, o5, o6, o7, o8};
+            const bool wn[8] = {wxm, wym, wxp, wyp, w5, w6, w7, w8};
+            float rsum = 0.0f;
+            int cnt = 0;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) d[i] = 0.0f;
+            for (int k = 0; k < 8; ++k) {
+                if (!wn[k] && flin.ld(on[k], 0) > 0.0f) {
+                    float r = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) r += fin.ld(on[k], (off_t)i * pb);
+                    rsum += r;
+                    ++cnt;
+                }
+            }
+            const float drho = cnt ? rsum * frcp((float)cnt) : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] = w9(i) * drho;
             Ac = stat.ld(o, pb);
             Bc = stat.ld(o, 2 * pb);
         }

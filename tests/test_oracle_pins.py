@@ -658,3 +658,26 @@ def test_conduction_melting_with_diffusivity_ratio():
     Tan = np.where(x <= xm, 1 - erf(x / (2 * math.sqrt(a_l * t))) / erf(eta),
                    -1 + erfc(x / (2 * math.sqrt(a_s * t))) / erfc(eta * math.sqrt(r)))
     assert np.abs(F["T"][0] - Tan).max() < 0.02
+
+
+def test_melting_node_joins_at_the_local_density(oracle_mod):
+    """Sec. 4 (flow solved in the liquid only), with the restart reading: a
+    node that melts inside a liquid at rest of uniform density rho takes that
+    density, so the liquid stays exactly at rest (no pressure pulse) and the
+    total mass grows by rho, not rho0."""
+    n, rho = 5, 1.013
+    c = W.make_case("join", n, n, [0] * 4, [0] * 4, Ra=0, Da=1e-2, Pr=1, Ste=1, eps=0.6,
+                    T_init=0.5, T_s=0.1, T_l=0.2, convective=0)
+    o = oracle_from_case(c)
+    w9, w5 = oracle_mod.lattice()["w9"], oracle_mod.lattice()["w5"]
+    fl = np.ones((n, n)); fl[2, 2] = 0.0
+    f = np.broadcast_to(w9[:, None, None] * rho, (9, n, n)).copy()
+    f[:, 2, 2] = 0.0
+    g = np.broadcast_to(w5[:, None, None] * 0.5, (5, n, n)).copy()
+    o.set_state(f, g, fl)
+    o.step(1)
+    fs, _, fls = o.get_state()
+    assert fls[2, 2] > 0
+    np.testing.assert_allclose(fs, np.broadcast_to(w9[:, None, None] * rho, fs.shape), atol=1e-15)
+    F = o.fields()
+    assert np.abs(F["ux"]).max() < 1e-16 and np.abs(F["uy"]).max() < 1e-16
