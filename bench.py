@@ -136,11 +136,15 @@ def main():
     fluid_frac = act_steps / (cells * args.steps)
     bytes_per_launch = (BYTES_FLUID * fluid_frac + BYTES_SOLID * (1 - fluid_frac)) * cells
     achieved = bytes_per_launch / (kern_ms * 1e-3)
+    # measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, two
+    # phase mixes solved for bytes per solid and per liquid node), valid while
+    # the step kernel source is the one that was measured
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if os.path.exists(TRAFFIC_FILE) and args.n == 1024:
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_sha") == kernel_hash() and tr.get("steps") == args.steps:
-            traffic = tr.get("bytes_per_launch")
+        if tr.get("kernel_sha") == kernel_hash():
+            traffic = round((tr["bytes_per_cell_solid"] * (1 - fluid_frac) +
+                             tr["bytes_per_cell_fluid"] * fluid_frac) * cells)
 
     out = {
         "metric": "MLUPS (flow+thermal)",
