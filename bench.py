@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="lattice side")
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--block-rows", type=int, default=0, help="step-kernel block rows (0: auto)")
+    ap.add_argument("--cells-per-lane", type=int, default=0, help="nodes per lane (0: auto)")
     ap.add_argument("--T-init", type=float, default=0.0,
                     help="initial temperature (0: solid start as in the workload; "
                          "0.5: liquid start, the flow is solved almost everywhere)")
@@ -97,7 +98,8 @@ def main():
 
     torch.cuda.set_device(0)
     case = W.cavity(nx=args.n, ny=args.n, steps=args.steps, T_init=args.T_init)
-    over = dict(graph_steps=args.graph_steps, block_rows=args.block_rows)
+    over = dict(graph_steps=args.graph_steps, block_rows=args.block_rows,
+                cells_per_lane=args.cells_per_lane)
 
     if args.copy_probe:
         a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -164,7 +166,7 @@ def main():
                                "seed 3), initial theta %g, steps 0..%d"
                                % (args.n, args.n, args.T_init, args.steps),
                    "nx": args.n, "ny": args.n, "graph_steps": args.graph_steps,
-                   "block_rows": args.block_rows,
+                   "block_rows": args.block_rows, "cells_per_lane": args.cells_per_lane,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),

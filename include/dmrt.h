@@ -89,7 +89,8 @@ typedef struct {
                            steps and returns DMRT_ENONFINITE; 0: never                 */
     int32_t graph_steps;/* >0: dmrt_step replays a captured HIP graph of this many
                            steps (even); 0: plain launches, default 0                  */
-    int32_t block_rows; /* rows per step-kernel block: 4, 8 or 16; 0 picks by size    */
+    int32_t block_rows; /* rows per step-kernel block: 4 or 8; 0 = 4                   */
+    int32_t cells_per_lane; /* nodes per lane in the step kernel: 1 or 2; 0 = 1       */
     void *stream;       /* hipStream_t for all work; NULL = null stream                 */
 } dmrt_opts;
 

@@ -118,8 +118,10 @@ int check_opts(const dmrt_opts& o)
     if (!finite_pos(o.ergun_c)) return fail(DMRT_EINVAL, "ergun_c must be > 0");
     if (o.check_every < 0 || o.graph_steps < 0 || (o.graph_steps & 1))
         return fail(DMRT_EINVAL, "check_every must be >= 0 and graph_steps even and >= 0");
-    if (o.block_rows != 0 && o.block_rows != 4 && o.block_rows != 8 && o.block_rows != 16)
-        return fail(DMRT_EINVAL, "block_rows must be 0, 4, 8 or 16");
+    if (o.block_rows != 0 && o.block_rows != 4 && o.block_rows != 8)
+        return fail(DMRT_EINVAL, "block_rows must be 0, 4 or 8");
+    if (o.cells_per_lane < 0 || o.cells_per_lane > 2)
+        return fail(DMRT_EINVAL, "cells_per_lane must be 0, 1 or 2");
     return DMRT_OK;
 }
 
@@ -170,6 +172,27 @@ void fill_phys(dmrt* h, const dmrt_opts& o)
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Tiling constants of the step kernel, including the magic number that
+// divides a tile index by the tiles per row (Granlund & Montgomery, unsigned
+// 32-bit "add" form: l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1).
+void set_step_tiling(Geom& G)
+{
+    const int rows = G.block_rows * G.cells_per_lane;
+    G.st_tx = (G.nx + dmrtk::TX - 1) / dmrtk::TX;
+    G.st_ntiles = G.st_tx * ((G.ny + rows - 1) / rows);
+    G.st_per_xcd = (G.st_ntiles + dmrtk::NXCD - 1) / dmrtk::NXCD;
+    const uint32_t d = (uint32_t)G.st_tx;
+    if (d == 1) {
+        G.st_magic = 0;
+        G.st_shift = 0;
+    } else {
+        int l = 0;
+        while ((1ull << l) < d) ++l;
+        G.st_magic = (uint32_t)(((((uint64_t)1 << l) - d) << 32) / d + 1);
+        G.st_shift = l;
+    }
+}
 
 int copy_in(void* dst, const void* src, size_t bytes, hipStream_t s)
 {
@@ -333,6 +356,7 @@ void dmrt_opts_default(dmrt_opts* o)
     o->check_every = 0;
     o->graph_steps = 0;
     o->block_rows = 0;
+    o->cells_per_lane = 0;
     o->stream = nullptr;
 }
 
@@ -381,6 +405,8 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
         G.T_wall[k] = (float)bc->T_wall[k];
     }
     G.block_rows = o.block_rows ? o.block_rows : 4;
+    G.cells_per_lane = o.cells_per_lane ? o.cells_per_lane : 1;
+    set_step_tiling(G);
     // 32-bit buffer addressing while the largest array (9 planes) fits 4 GB
     G.wide = (uint64_t)G.plane * 4 * 9 >= (1ull << 32) ? 1 : 0;
     fill_phys(h, o);

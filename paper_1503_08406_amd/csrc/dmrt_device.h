@@ -34,6 +34,42 @@ __device__ __forceinline__ bool tile_coords(const Geom& G, int& x, int& y)
     return x < G.nx && y < G.ny;
 }
 
+// Origin of this block's tile of 64 x ROWS nodes (same mapping).
+template <int ROWS>
+__device__ __forceinline__ bool tile_origin(const Geom& G, int& x0, int& y0)
+{
+    const int tiles_x = (G.nx + TX - 1) / TX;
+    const int ntiles = tiles_x * ((G.ny + ROWS - 1) / ROWS);
+    const int per_xcd = (ntiles + NXCD - 1) / NXCD;
+    const int b = blockIdx.x;
+    const int tile = (b % NXCD) * per_xcd + b / NXCD;
+    if (tile >= ntiles) return false;
+    x0 = (tile % tiles_x) * TX;
+    y0 = (tile / tiles_x) * ROWS;
+    return true;
+}
+
+// Tile origin of the step kernel from the host-computed tiling constants:
+// q = tile / st_tx via q = (hi + ((t - hi) >> 1)) >> (shift - 1), hi =
+// mulhi(t, magic) (division by an invariant integer, Granlund & Montgomery).
+template <int ROWS>
+__device__ __forceinline__ bool step_tile_origin(const Geom& G, int& x0, int& y0)
+{
+    const uint32_t b = blockIdx.x;
+    const uint32_t tile = (b & (NXCD - 1)) * (uint32_t)G.st_per_xcd + (b >> 3);
+    if (tile >= (uint32_t)G.st_ntiles) return false;
+    uint32_t q;
+    if (G.st_shift == 0) {
+        q = tile;  // one tile per row
+    } else {
+        const uint32_t hi = __umulhi(tile, G.st_magic);
+        q = (hi + ((tile - hi) >> 1)) >> (G.st_shift - 1);
+    }
+    x0 = (int)(tile - q * (uint32_t)G.st_tx) * TX;
+    y0 = (int)q * ROWS;
+    return true;
+}
+
 inline int tile_blocks(const Geom& G, int TYB)
 {
     const int tiles_x = (G.nx + TX - 1) / TX;
@@ -55,11 +91,15 @@ struct BufIO {
     __device__ __forceinline__ float ld(off_t o, off_t plane_off) const
     {
         // the b32 buffer intrinsics move raw 32-bit words: bit-cast, never convert
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, plane_off, 0));
+        // plane offsets are uniform; readfirstlane keeps them in SGPRs (the
+        // buffer instruction's soffset) instead of a per-lane waterfall loop
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                             r, o, __builtin_amdgcn_readfirstlane(plane_off), 0));
     }
     __device__ __forceinline__ void st(off_t o, off_t plane_off, float v) const
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, plane_off, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o,
+                                              __builtin_amdgcn_readfirstlane(plane_off), 0);
     }
 };
 

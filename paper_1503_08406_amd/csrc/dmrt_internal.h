@@ -40,7 +40,14 @@ struct Geom {
     int per_x, per_y;   // periodic axes
     int wall_T[4];      // side x-, x+, y-, y+: 1 fixed temperature, 0 adiabatic
     float T_wall[4];
-    int block_rows;     // rows of a step-kernel block (4, 8 or 16)
+    int block_rows;     // rows of a step-kernel block (4 or 8)
+    int cells_per_lane; // nodes per lane in the step kernel (1 or 2)
+    // tiling of the step kernel (tiles of 64 x block_rows*cells_per_lane):
+    // tiles per row, tiles in total, tiles per die, and the Granlund-
+    // Montgomery magic (multiplier, shift) dividing a tile index by st_tx
+    int st_tx, st_ntiles, st_per_xcd;
+    uint32_t st_magic;
+    int st_shift;
     int wide;           // 1: 64-bit addressing (arrays beyond a 4 GB window)
 };
 

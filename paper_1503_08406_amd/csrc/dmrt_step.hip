@@ -25,54 +25,107 @@
 namespace dmrtk {
 namespace {
 
-template <class IO, bool FLOW, bool COUNT, int TYB>
-__global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
+// The state arrays of one launch.
+template <class IO>
+struct Arrays {
+    typename IO::off_t pb;  // bytes per population plane
+    IO fin, fout, gin, gout, flin, flout, uv, stat;
+    __device__ __forceinline__ Arrays(const Geom& G, const StepBufs& B)
+        : pb((typename IO::off_t)G.plane * 4u),
+          fin(B.fin, 9 * (uint64_t)pb), fout(B.fout, 9 * (uint64_t)pb),
+          gin(B.gin, 5 * (uint64_t)pb), gout(B.gout, 5 * (uint64_t)pb),
+          flin(B.flin, pb), flout(B.flout, pb),
+          uv(B.ux, 2 * (uint64_t)pb),    // ux plane, then uy plane
+          stat(B.eps, 3 * (uint64_t)pb)  // eps, Ac, Bc planes
+    {
+    }
+};
+
+// A node between its first load batch and the rest of its step.
+template <class IO>
+struct Node {
+    typename IO::off_t o, o1, o2, o3, o4;
+    int xm, xp, ym, yp;
+    float flk, eps, g[5];
+    int x, y;
+};
+
+// Offsets of node (x, y) and its first load batch: f_l^k, porosity and the
+// five g pulls (every node needs them, liquid or solid).
+template <class IO>
+__device__ __forceinline__ void node_load(const Geom& G, const Arrays<IO>& A, int x, int y,
+                                          Node<IO>& n)
 {
     using off_t = typename IO::off_t;
-    int x, y;
-    if (!tile_coords<TYB>(G, x, y)) return;
-    const off_t pb = (off_t)G.plane * 4u;  // bytes per population plane
-    const IO fin(B.fin, 9 * (uint64_t)pb), fout(B.fout, 9 * (uint64_t)pb);
-    const IO gin(B.gin, 5 * (uint64_t)pb), gout(B.gout, 5 * (uint64_t)pb);
-    const IO flin(B.flin, pb), flout(B.flout, pb);
-    const IO uv(B.ux, 2 * (uint64_t)pb);    // ux plane, then uy plane
-    const IO stat(B.eps, 3 * (uint64_t)pb);  // eps, Ac, Bc planes
-
-    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-    bool wxm = false, wxp = false, wym = false, wyp = false;
-    if (xm < 0) { if (G.per_x) xm += G.nx; else wxm = true; }
-    if (xp >= G.nx) { if (G.per_x) xp -= G.nx; else wxp = true; }
-    if (ym < 0) { if (G.per_y) ym += G.ny; else wym = true; }
-    if (yp >= G.ny) { if (G.per_y) yp -= G.ny; else wyp = true; }
+    n.x = x;
+    n.y = y;
+    // neighbour indices without branches: wrap on periodic axes, a wall flag
+    // (and any in-bounds index) otherwise
+    const bool xlo = x == 0, xhi = x == G.nx - 1, ylo = y == 0, yhi = y == G.ny - 1;
+    const bool wxm = xlo & !G.per_x, wxp = xhi & !G.per_x;
+    const bool wym = ylo & !G.per_y, wyp = yhi & !G.per_y;
+    const int xm = xlo ? G.nx - 1 : x - 1, xp = xhi ? 0 : x + 1;
+    const int ym = ylo ? G.ny - 1 : y - 1, yp = yhi ? 0 : y + 1;
     const off_t pitch = (off_t)G.pitch;
-    const off_t r0 = (off_t)y * pitch, rm = (off_t)ym * pitch, rp = (off_t)yp * pitch;
+    const off_t r0 = (off_t)y * pitch;
     const off_t o = (r0 + (off_t)x) * 4u;
-    const bool w5 = wxm | wym, w6 = wxp | wym, w7 = wxp | wyp, w8 = wxm | wyp;
-    const bool wall = wxm | wxp | wym | wyp;
     // byte offsets of the sources x - e_i; a source behind a wall is pointed
-    // at the node itself (always in bounds) and its value is replaced below,
-    // so every pull is an unconditional load
-    const off_t o1 = wxm ? o : (r0 + (off_t)xm) * 4u, o3 = wxp ? o : (r0 + (off_t)xp) * 4u;
-    const off_t o2 = wym ? o : (rm + (off_t)x) * 4u, o4 = wyp ? o : (rp + (off_t)x) * 4u;
-    const off_t o5 = w5 ? o : (rm + (off_t)xm) * 4u, o6 = w6 ? o : (rm + (off_t)xp) * 4u;
-    const off_t o7 = w7 ? o : (rp + (off_t)xp) * 4u, o8 = w8 ? o : (rp + (off_t)xm) * 4u;
+    // at the node itself (always in bounds) and its value is replaced later,
+    // so every pull is an unconditional load.  Diagonal offsets are formed
+    // only for liquid nodes (node_finish).
+    n.o = o;
+    n.o1 = wxm ? o : (r0 + (off_t)xm) * 4u;
+    n.o3 = wxp ? o : (r0 + (off_t)xp) * 4u;
+    n.o2 = wym ? o : ((off_t)ym * pitch + (off_t)x) * 4u;
+    n.o4 = wyp ? o : ((off_t)yp * pitch + (off_t)x) * 4u;
+    n.xm = xm;
+    n.xp = xp;
+    n.ym = ym;
+    n.yp = yp;
+    const off_t pb = A.pb;
+    n.flk = A.flin.ld(o, 0);
+    n.eps = A.stat.ld(o, 0);
+    n.g[0] = A.gin.ld(o, 0);
+    n.g[1] = A.gin.ld(n.o1, pb);
+    n.g[2] = A.gin.ld(n.o2, 2 * pb);
+    n.g[3] = A.gin.ld(n.o3, 3 * pb);
+    n.g[4] = A.gin.ld(n.o4, 4 * pb);
+}
 
-    const float flk = flin.ld(o, 0);
+// The rest of the step of one node (see the top of this file).
+template <class IO, bool FLOW, bool COUNT>
+__device__ __forceinline__ void node_finish(const Geom& G, const Phys& P, const StepBufs& B,
+                                            const Arrays<IO>& A, Node<IO>& n)
+{
+    using off_t = typename IO::off_t;
+    const off_t pb = A.pb;
+    const IO &fin = A.fin, &fout = A.fout, &gin = A.gin, &gout = A.gout;
+    const IO &flin = A.flin, &flout = A.flout, &uv = A.uv, &stat = A.stat;
+    const off_t o = n.o, o1 = n.o1, o2 = n.o2, o3 = n.o3, o4 = n.o4;
+    const bool wxm = (n.x == 0) & !G.per_x, wxp = (n.x == G.nx - 1) & !G.per_x;
+    const bool wym = (n.y == 0) & !G.per_y, wyp = (n.y == G.ny - 1) & !G.per_y;
+    const bool w5 = wxm | wym, w6 = wxp | wym, w7 = wxp | wyp, w8 = wxm | wyp;
+    off_t o5 = o, o6 = o, o7 = o, o8 = o;  // diagonal sources, formed where needed
+    const auto diag_offsets = [&]() {
+        const off_t pitch = (off_t)G.pitch;
+        const off_t rm = (off_t)n.ym * pitch, rp = (off_t)n.yp * pitch;
+        o5 = w5 ? o : (rm + (off_t)n.xm) * 4u;
+        o6 = w6 ? o : (rm + (off_t)n.xp) * 4u;
+        o7 = w7 ? o : (rp + (off_t)n.xp) * 4u;
+        o8 = w8 ? o : (rp + (off_t)n.xm) * 4u;
+    };
+    const bool wall = wxm | wxp | wym | wyp;
+    const int x = n.x, y = n.y;
+    const float flk = n.flk, eps = n.eps;
+    float (&g)[5] = n.g;
     const bool act0 = FLOW && flk > 0.0f;
 
-    // ---- all pulls of this node, issued together
-    const float eps = stat.ld(o, 0);
-    float g[5];
-    g[0] = gin.ld(o, 0);
-    g[1] = gin.ld(o1, pb);
-    g[2] = gin.ld(o2, 2 * pb);
-    g[3] = gin.ld(o3, 3 * pb);
-    g[4] = gin.ld(o4, 4 * pb);
     float d[9];
     bool nee_f = false;
     unsigned liq = 0;  // bit i set: source of direction i is a liquid node
     float Ac = 0.0f, Bc = 0.0f;
     if (act0) {
+        diag_offsets();
         const float n1 = flin.ld(o1, 0), n2 = flin.ld(o2, 0), n3 = flin.ld(o3, 0);
         const float n4 = flin.ld(o4, 0), n5 = flin.ld(o5, 0), n6 = flin.ld(o6, 0);
         const float n7 = flin.ld(o7, 0), n8 = flin.ld(o8, 0);
@@ -180,6 +233,7 @@ __global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
             // start-of-step density of its liquid neighbours (rho0 if none),
             // f_i = w_i rho_bar; rho - 1 of a neighbour is the sum of its
             // stored post-collision deviations (collision conserves mass)
+            diag_offsets();
             const off_t on[8] = {o1, o2, o3, o4, o5, o6, o7, o8};
             const bool wn[8] = {wxm, wym, wxp, wyp, w5, w6, w7, w8};
             float rsum = 0.0f;
@@ -213,22 +267,42 @@ __global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
     flout.st(o, 0, fl1);
 }
 
+
+template <class IO, bool FLOW, bool COUNT, int TYB, int CPT>
+__global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
+{
+    // a tile of 64 x (TYB * CPT) nodes; a lane owns CPT nodes TYB rows apart
+    // and issues the first load batch of all of them before finishing any
+    int x0, y0;
+    if (!step_tile_origin<TYB * CPT>(G, x0, y0)) return;
+    const Arrays<IO> A(G, B);
+    const int x = x0 + (int)threadIdx.x;
+    Node<IO> n[CPT];
+    bool ok[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int y = y0 + (int)threadIdx.y + j * TYB;
+        ok[j] = x < G.nx && y < G.ny;
+        if (ok[j]) node_load<IO>(G, A, x, y, n[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+        if (ok[j]) node_finish<IO, FLOW, COUNT>(G, P, B, A, n[j]);
+}
+
 template <class IO, bool FLOW, bool COUNT>
 hipError_t launch_rows(const Geom& G, const Phys& P, const StepBufs& B, hipStream_t s)
 {
-    const int rows = G.block_rows;
-    const dim3 grd(tile_blocks(G, rows));
-    switch (rows) {
-    case 8:
-        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 8>), grd, dim3(TX, 8), 0, s, G, P, B);
-        break;
-    case 16:
-        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 16>), grd, dim3(TX, 16), 0, s, G, P, B);
-        break;
-    default:
-        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 4>), grd, dim3(TX, 4), 0, s, G, P, B);
-        break;
-    }
+    const int rows = G.block_rows, cpt = G.cells_per_lane;
+    const dim3 grd(NXCD * G.st_per_xcd);
+    if (rows == 8 && cpt == 2)
+        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 8, 2>), grd, dim3(TX, 8), 0, s, G, P, B);
+    else if (rows == 8)
+        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 8, 1>), grd, dim3(TX, 8), 0, s, G, P, B);
+    else if (cpt == 2)
+        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 4, 2>), grd, dim3(TX, 4), 0, s, G, P, B);
+    else
+        hipLaunchKernelGGL((k_step<IO, FLOW, COUNT, 4, 1>), grd, dim3(TX, 4), 0, s, G, P, B);
     return hipGetLastError();
 }
 

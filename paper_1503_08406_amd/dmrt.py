@@ -36,7 +36,8 @@ class Opts(C.Structure):
                  "T_init", "alpha_l", "varpi", "s_e", "s_eps", "s_q", "zeta_e", "zeta_nu",
                  "ergun_c", "fl_tol")] + \
               [("fl_maxit", C.c_int32), ("convective", C.c_int32), ("check_every", C.c_int32),
-               ("graph_steps", C.c_int32), ("block_rows", C.c_int32), ("stream", C.c_void_p)]
+               ("graph_steps", C.c_int32), ("block_rows", C.c_int32), ("cells_per_lane", C.c_int32),
+               ("stream", C.c_void_p)]
 
 
 class Derived(C.Structure):
