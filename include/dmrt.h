@@ -185,6 +185,74 @@ int dmrt_sync(dmrt_t *h);
 /* Release the handle (NULL is ignored). */
 void dmrt_destroy(dmrt_t *h);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent cavities of uneven size and parameters advance
+ * together, one launch per time step over all of them.  Each cavity runs
+ * exactly the step of a single lattice created by dmrt_create with the same
+ * grid, boundary, dimensionless numbers and options and with uniform porous
+ * fields (eps everywhere, K = Da H^2, F_eps from the Ergun relation of
+ * Eq. 6), so its fields equal that lattice's bit for bit.  The flow part is
+ * always solved (a cavity with Ra == 0 stays at rest).
+ * ------------------------------------------------------------------------ */
+typedef struct dmrt_batch dmrt_batch_t;
+
+/* One cavity of a batch. */
+typedef struct {
+    dmrt_grid grid;
+    dmrt_bc bc;
+    double eps;                 /* uniform porosity, (0, 1]                  */
+    double Ra, Da, Pr, Ste;     /* as for dmrt_create                        */
+} dmrt_cavity;
+
+/* Create a batch of ncav >= 1 cavities on the current HIP device, every one
+ * initialised as dmrt_create does.  opts (may be NULL) applies to all
+ * cavities; its graph_steps and check_every act on the batch, block_rows
+ * picks the first launch shape (see dmrt_batch_set_launch) and
+ * cells_per_lane is ignored.  DMRT_EINVAL names the first bad cavity. */
+int dmrt_batch_create(int32_t ncav, const dmrt_cavity *cav, const dmrt_opts *opts,
+                      dmrt_batch_t **out);
+
+/* Advance every cavity n >= 0 time steps (enqueued). */
+int dmrt_batch_step(dmrt_batch_t *b, int64_t n);
+
+/* Fields of cavity i, as dmrt_fields (each pointer nx*ny floats of that
+ * cavity, any may be NULL). */
+int dmrt_batch_fields(dmrt_batch_t *b, int32_t i, float *T, float *ux, float *uy, float *fl);
+
+/* Per-cavity counts of liquid nodes (f_l > 0) and of NaN/Inf values in f_l
+ * and g; either array (ncav entries) may be NULL. */
+int dmrt_batch_check(dmrt_batch_t *b, int64_t *liquid, int64_t *nonfinite);
+
+/* Launch shape of the batched step: rows of a 64-wide tile (4 or 8) and the
+ * number of blocks (a multiple of 8; 0 = as many as the device holds at
+ * once).  The shape changes speed only, never results. */
+int dmrt_batch_set_launch(dmrt_batch_t *b, int32_t rows, int32_t blocks);
+int dmrt_batch_get_launch(const dmrt_batch_t *b, int32_t *rows, int32_t *blocks);
+
+/* Autotuner of the launch shape.  For every candidate (rows 4 and 8; as
+ * many blocks as the device holds at once, twice that, one block per tile)
+ * run trial_steps >= 1 untimed and then trial_steps timed steps from a copy
+ * of the current state; keep the fastest (dmrt_batch_set_launch) and
+ * restore the state, so results and the time counter are unchanged.  Any
+ * output pointer may be NULL; ms_per_step is the winner's mean step time. */
+int dmrt_batch_tune(dmrt_batch_t *b, int32_t trial_steps, int32_t *rows, int32_t *blocks,
+                    double *ms_per_step);
+
+/* Lattice constants of cavity i. */
+int dmrt_batch_get_derived(const dmrt_batch_t *b, int32_t i, dmrt_derived *out);
+
+/* Evolving nodes over all cavities (sum of nx * ny). */
+int64_t dmrt_batch_cells(const dmrt_batch_t *b);
+
+/* Time steps taken so far. */
+int64_t dmrt_batch_time(const dmrt_batch_t *b);
+
+/* Wait for the batch's stream. */
+int dmrt_batch_sync(dmrt_batch_t *b);
+
+/* Release the batch (NULL is ignored). */
+void dmrt_batch_destroy(dmrt_batch_t *b);
+
 /* Thread-local text of the last error ("" if none). */
 const char *dmrt_last_error(void);
 

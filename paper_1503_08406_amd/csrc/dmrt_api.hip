@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,7 +40,7 @@ int fail(int code, const char* fmt, ...)
                         #expr, hipGetErrorString(e_));                                      \
     } while (0)
 
-constexpr uint64_t kMagic = 0x314d52544d444d44ull;  // checkpoint tag
+constexpr uint64_t kMagic = 0x324d52544d444d44ull;  // checkpoint tag (layout 2: ten f planes)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
@@ -137,10 +138,8 @@ int check_bc(const dmrt_bc* bc)
     return DMRT_OK;
 }
 
-void fill_phys(dmrt* h, const dmrt_opts& o)
+void fill_phys(Phys& P, const dmrt_derived& d, double Ste, const dmrt_opts& o)
 {
-    Phys& P = h->P;
-    const dmrt_derived& d = h->D;
     P.s_e = (float)o.s_e;
     P.s_eps = (float)o.s_eps;
     P.s_q = (float)o.s_q;
@@ -158,8 +157,8 @@ void fill_phys(dmrt* h, const dmrt_opts& o)
     P.lam_as = (float)(o.lambda * d.alpha_s);
     P.dlam = (float)(o.lambda * (d.alpha_l - d.alpha_s));
     P.T_s = (float)o.T_s;
-    P.inv_St = (float)(1.0 / h->Ste);
-    P.inv_den = (float)(1.0 / (o.T_l - o.T_s + 1.0 / h->Ste));
+    P.inv_St = (float)(1.0 / Ste);
+    P.inv_den = (float)(1.0 / (o.T_l - o.T_s + 1.0 / Ste));
     P.inv_dTm = (float)(1.0 / (o.T_l - o.T_s));
     P.gbeta = (float)d.gbeta;
     P.T0 = (float)o.T0;
@@ -172,6 +171,28 @@ void fill_phys(dmrt* h, const dmrt_opts& o)
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+void set_step_tiling(Geom& G);
+
+// Lattice geometry, boundary description and launch shape of one lattice.
+void fill_geom(Geom& G, int nx, int ny, const dmrt_bc& bc, const dmrt_opts& o)
+{
+    G.nx = nx;
+    G.ny = ny;
+    G.pitch = (nx + 63) / 64 * 64;
+    G.plane = (long long)ny * G.pitch;
+    G.per_x = bc.kind[0] == DMRT_PERIODIC;
+    G.per_y = bc.kind[2] == DMRT_PERIODIC;
+    for (int k = 0; k < 4; ++k) {
+        G.wall_T[k] = bc.kind[k] == DMRT_WALL_T;
+        G.T_wall[k] = (float)bc.T_wall[k];
+    }
+    G.block_rows = o.block_rows ? o.block_rows : 4;
+    G.cells_per_lane = o.cells_per_lane ? o.cells_per_lane : 1;
+    // 32-bit buffer addressing while the largest array (9 planes) fits 4 GB
+    G.wide = (uint64_t)G.plane * 4 * dmrtk::FQ >= (1ull << 32) ? 1 : 0;
+    set_step_tiling(G);
+}
 
 // Tiling constants of the step kernel, including the magic number that
 // divides a tile index by the tiles per row (Granlund & Montgomery, unsigned
@@ -394,22 +415,8 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     h->graph_steps = o.graph_steps;
     h->stream = (hipStream_t)o.stream;
     Geom& G = h->G;
-    G.nx = (int)nx;
-    G.ny = (int)ny;
-    G.pitch = (int)pitch;
-    G.plane = ny * pitch;
-    G.per_x = bc->kind[0] == DMRT_PERIODIC;
-    G.per_y = bc->kind[2] == DMRT_PERIODIC;
-    for (int k = 0; k < 4; ++k) {
-        G.wall_T[k] = bc->kind[k] == DMRT_WALL_T;
-        G.T_wall[k] = (float)bc->T_wall[k];
-    }
-    G.block_rows = o.block_rows ? o.block_rows : 4;
-    G.cells_per_lane = o.cells_per_lane ? o.cells_per_lane : 1;
-    set_step_tiling(G);
-    // 32-bit buffer addressing while the largest array (9 planes) fits 4 GB
-    G.wide = (uint64_t)G.plane * 4 * 9 >= (1ull << 32) ? 1 : 0;
-    fill_phys(h, o);
+    fill_geom(G, (int)nx, (int)ny, *bc, o);
+    fill_phys(h->P, h->D, h->Ste, o);
     h->flow = d.gbeta != 0.0;
 
     auto bail = [&](int code) {
@@ -453,7 +460,7 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
 
     // Device memory: one allocation, 256-byte aligned sub-arrays.
     const size_t plane_b = align256(pcell * sizeof(float));
-    const size_t total = plane_b * (2 * 9 + 2 * 5 + 2 + 2 + 3);
+    const size_t total = plane_b * (2 * dmrtk::FQ + 2 * 5 + 2 + 2 + 3);
     e = hipMalloc(&h->base, total);
     if (e != hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE,
@@ -464,8 +471,8 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
         p += planes * plane_b;
         return r;
     };
-    h->f[0] = take(9);
-    h->f[1] = take(9);
+    h->f[0] = take(dmrtk::FQ);
+    h->f[1] = take(dmrtk::FQ);
     h->g[0] = take(5);
     h->g[1] = take(5);
     h->fl[0] = take(1);
@@ -631,7 +638,7 @@ int dmrt_get_derived(const dmrt_t* h, dmrt_derived* out)
 int64_t dmrt_state_bytes(const dmrt_t* h)
 {
     if (!h) return fail(DMRT_EINVAL, "null handle");
-    return (int64_t)(64 + (size_t)h->G.plane * 17 * sizeof(float));
+    return (int64_t)(64 + (size_t)h->G.plane * (dmrtk::FQ + 8) * sizeof(float));
 }
 
 int dmrt_save(dmrt_t* h, void* buf, size_t cap)
@@ -646,11 +653,12 @@ int dmrt_save(dmrt_t* h, void* buf, size_t cap)
     char* p = (char*)buf + 64;
     const size_t pb = (size_t)h->G.plane * sizeof(float);
     const int a = h->cur;
-    HIPCHK(hipMemcpyAsync(p, h->f[a], 9 * pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(p + 9 * pb, h->g[a], 5 * pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(p + 14 * pb, h->fl[a], pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(p + 15 * pb, h->ux, pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(p + 16 * pb, h->uy, pb, hipMemcpyDefault, h->stream));
+    const size_t fq = dmrtk::FQ;
+    HIPCHK(hipMemcpyAsync(p, h->f[a], fq * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + fq * pb, h->g[a], 5 * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + (fq + 5) * pb, h->fl[a], pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + (fq + 6) * pb, h->ux, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + (fq + 7) * pb, h->uy, pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return DMRT_OK;
 }
@@ -668,11 +676,12 @@ int dmrt_load(dmrt_t* h, const void* buf, size_t n)
     const char* p = (const char*)buf + 64;
     const size_t pb = (size_t)h->G.plane * sizeof(float);
     const int a = h->cur;
-    HIPCHK(hipMemcpyAsync(h->f[a], p, 9 * pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(h->g[a], p + 9 * pb, 5 * pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(h->fl[a], p + 14 * pb, pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(h->ux, p + 15 * pb, pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(h->uy, p + 16 * pb, pb, hipMemcpyDefault, h->stream));
+    const size_t fq = dmrtk::FQ;
+    HIPCHK(hipMemcpyAsync(h->f[a], p, fq * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->g[a], p + fq * pb, 5 * pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->fl[a], p + (fq + 5) * pb, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->ux, p + (fq + 6) * pb, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->uy, p + (fq + 7) * pb, pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->t = (int64_t)hdr[4];
     h->flow = h->flow || hdr[5] != 0;
@@ -703,5 +712,491 @@ void dmrt_destroy(dmrt_t* h)
 }
 
 const char* dmrt_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent cavities.
+//
+// Every cavity keeps its own planes, laid out as for a single lattice (row
+// pitch a multiple of 64), inside one arena per array kind: f (9 planes),
+// g (5), f_l (1), each double-buffered, and u (2 planes).  A device table of
+// Cavity headers gives each cavity's geometry, constants, uniform porous
+// values and plane offsets; a device tile list names (cavity, x0, y0) for
+// every 64 x rows tile.  One launch per time step covers the whole list.
+// ---------------------------------------------------------------------------
+
+struct dmrt_batch {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    int ncav = 0;
+    std::vector<dmrtk::Cavity> cav;
+    std::vector<dmrt_derived> D;
+    int64_t cells = 0;
+    int cur = 0;
+    int64_t t = 0;
+    int check_every = 0, graph_steps = 0;
+    int rows = 4, blocks = 0, launch_blocks = 0;
+    int die[dmrtk::NXCD + 1]{};
+    size_t f_len = 0, g_len = 0, fl_len = 0, u_len = 0;  // arena lengths in floats
+    char* base = nullptr;
+    float *f[2]{}, *g[2]{}, *fl[2]{}, *u = nullptr;
+    dmrtk::Cavity* dcav = nullptr;
+    int4* dtiles = nullptr;
+    size_t tiles_cap = 0;
+    long long* partials = nullptr;
+    hipGraphExec_t graph[2]{};
+};
+
+namespace {
+
+constexpr int kCountBlocks = 16;  // partial-count blocks per cavity
+
+void drop_graphs(dmrt_batch* b)
+{
+    for (auto& g : b->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Tile list for tiles of 64 x rows nodes, cut into one contiguous part per
+// die with about equal node counts; block count of the launch.
+int batch_layout(dmrt_batch* b, int rows, int blocks)
+{
+    std::vector<int4> tl;
+    std::vector<long long> w;
+    for (int c = 0; c < b->ncav; ++c) {
+        const Geom& G = b->cav[c].G;
+        for (int y0 = 0; y0 < G.ny; y0 += rows)
+            for (int x0 = 0; x0 < G.nx; x0 += dmrtk::TX) {
+                tl.push_back(make_int4(c, x0, y0, 0));
+                w.push_back((long long)std::min(dmrtk::TX, G.nx - x0) * std::min(rows, G.ny - y0));
+            }
+    }
+    const int nt = (int)tl.size();
+    long long total = 0;
+    for (long long v : w) total += v;
+    int d = 1;
+    long long acc = 0;
+    b->die[0] = 0;
+    for (int k = 0; k < nt && d < dmrtk::NXCD; ++k) {
+        acc += w[k];
+        while (d < dmrtk::NXCD && acc * dmrtk::NXCD >= total * d) b->die[d++] = k + 1;
+    }
+    while (d <= dmrtk::NXCD) b->die[d++] = nt;
+    int most = 0;
+    for (int k = 0; k < dmrtk::NXCD; ++k) most = std::max(most, b->die[k + 1] - b->die[k]);
+    int nb = blocks;
+    if (nb == 0) {
+        int ncu = 0;
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->dev));
+        nb = dmrtk::batch_blocks_per_cu(rows) * ncu / dmrtk::NXCD * dmrtk::NXCD;
+    }
+    // no die needs more blocks than it has tiles
+    nb = std::max(dmrtk::NXCD, std::min(nb, dmrtk::NXCD * most));
+    if ((size_t)nt > b->tiles_cap) {
+        if (b->dtiles) HIPCHK(hipFree(b->dtiles));
+        b->dtiles = nullptr;
+        b->tiles_cap = 0;
+        HIPCHK(hipMalloc(&b->dtiles, (size_t)nt * sizeof(int4)));
+        b->tiles_cap = (size_t)nt;
+    }
+    HIPCHK(hipMemcpyAsync(b->dtiles, tl.data(), (size_t)nt * sizeof(int4), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    b->rows = rows;
+    b->blocks = blocks;
+    b->launch_blocks = nb;
+    return DMRT_OK;
+}
+
+dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p)
+{
+    dmrtk::BatchArgs a;
+    a.cav = b->dcav;
+    a.tiles = b->dtiles;
+    for (int k = 0; k <= dmrtk::NXCD; ++k) a.die[k] = b->die[k];
+    a.fin = b->f[p];
+    a.fout = b->f[1 - p];
+    a.gin = b->g[p];
+    a.gout = b->g[1 - p];
+    a.flin = b->fl[p];
+    a.flout = b->fl[1 - p];
+    a.u = b->u;
+    return a;
+}
+
+int batch_graph(dmrt_batch* b, int p)
+{
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int q = p;
+    for (int k = 0; k < b->graph_steps; ++k) {
+        hipError_t e = dmrtk::launch_batch_step(batch_args(b, q), b->rows, b->launch_blocks,
+                                                b->stream);
+        q = 1 - q;
+        if (e != hipSuccess) {
+            hipGraph_t gdrop = nullptr;
+            (void)hipStreamEndCapture(b->stream, &gdrop);
+            if (gdrop) (void)hipGraphDestroy(gdrop);
+            return fail(DMRT_EDEVICE, "launch during capture: %s", hipGetErrorString(e));
+        }
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamEndCapture(b->stream, &graph));
+    hipError_t e = hipGraphInstantiate(&b->graph[p], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return DMRT_OK;
+}
+
+int batch_counts(dmrt_batch* b, std::vector<long long>& liq, std::vector<long long>& bad)
+{
+    const int a = b->cur;
+    HIPCHK(dmrtk::launch_batch_count(b->dcav, b->ncav, b->fl[a], b->g[a], b->partials,
+                                     kCountBlocks, b->stream));
+    std::vector<long long> hp((size_t)2 * kCountBlocks * b->ncav);
+    HIPCHK(hipMemcpyAsync(hp.data(), b->partials, hp.size() * sizeof(long long),
+                          hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    liq.assign(b->ncav, 0);
+    bad.assign(b->ncav, 0);
+    for (int c = 0; c < b->ncav; ++c)
+        for (int k = 0; k < kCountBlocks; ++k) {
+            liq[c] += hp[2 * ((size_t)c * kCountBlocks + k)];
+            bad[c] += hp[2 * ((size_t)c * kCountBlocks + k) + 1];
+        }
+    return DMRT_OK;
+}
+
+int batch_check_finite(dmrt_batch* b)
+{
+    std::vector<long long> liq, bad;
+    int rc = batch_counts(b, liq, bad);
+    if (rc) return rc;
+    for (int c = 0; c < b->ncav; ++c)
+        if (bad[c])
+            return fail(DMRT_ENONFINITE, "cavity %d: non-finite state at step %lld (%lld values)",
+                        c, (long long)b->t, bad[c]);
+    return DMRT_OK;
+}
+
+int batch_step_impl(dmrt_batch* b, int64_t n)
+{
+    int64_t since_check = 0;
+    while (n > 0) {
+        int64_t chunk = 1;
+        if (b->graph_steps > 0 && b->stream && n >= b->graph_steps &&
+            (b->check_every == 0 || b->check_every - since_check >= b->graph_steps)) {
+            const int p = b->cur;
+            if (!b->graph[p]) {
+                int rc = batch_graph(b, p);
+                if (rc) return rc;
+            }
+            HIPCHK(hipGraphLaunch(b->graph[p], b->stream));
+            chunk = b->graph_steps;  // even: parity unchanged
+        } else {
+            HIPCHK(dmrtk::launch_batch_step(batch_args(b, b->cur), b->rows, b->launch_blocks,
+                                            b->stream));
+            b->cur = 1 - b->cur;
+        }
+        b->t += chunk;
+        n -= chunk;
+        since_check += chunk;
+        if (b->check_every > 0 && since_check >= b->check_every) {
+            since_check = 0;
+            int rc = batch_check_finite(b);
+            if (rc) return rc;
+        }
+    }
+    return DMRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opts,
+                      dmrt_batch_t** out)
+{
+    g_err.clear();
+    if (!out) return fail(DMRT_EINVAL, "null output handle");
+    *out = nullptr;
+    if (ncav < 1 || !cav) return fail(DMRT_EINVAL, "need at least one cavity");
+    dmrt_opts o;
+    if (opts) o = *opts; else dmrt_opts_default(&o);
+    int rc = check_opts(o);
+    if (rc) return rc;
+
+    dmrt_batch* b = new (std::nothrow) dmrt_batch;
+    if (!b) return fail(DMRT_ENOMEM, "host allocation");
+    auto bail = [&](int code) {
+        dmrt_batch_destroy(b);
+        return code;
+    };
+    b->ncav = ncav;
+    b->stream = (hipStream_t)o.stream;
+    b->check_every = o.check_every;
+    b->graph_steps = o.graph_steps;
+    b->cav.resize(ncav);
+    b->D.resize(ncav);
+    for (int c = 0; c < ncav; ++c) {
+        const dmrt_cavity& in = cav[c];
+        dmrt_derived& d = b->D[c];
+        if ((rc = derive_impl(&in.grid, in.Ra, in.Da, in.Pr, in.Ste, o, &d)) || (rc = check_bc(&in.bc))) {
+            const std::string why = g_err;
+            return bail(fail(rc, "cavity %d: %s", c, why.c_str()));
+        }
+        const long long pitch = ((long long)in.grid.nx + 63) / 64 * 64;
+        if ((long long)in.grid.ny * pitch * 4 * dmrtk::FQ >= (1ll << 32))
+            return bail(fail(DMRT_EINVAL, "cavity %d: lattice too large for a batch", c));
+        // the porous values of a single lattice with this porosity everywhere
+        const double ep = (double)(float)in.eps;
+        if (!(ep > 0.0 && ep <= 1.0))
+            return bail(fail(DMRT_EINVAL, "cavity %d: eps = %g outside (0, 1]", c, in.eps));
+        dmrtk::Cavity& C = b->cav[c];
+        std::memset(&C, 0, sizeof C);
+        fill_geom(C.G, in.grid.nx, in.grid.ny, in.bc, o);
+        fill_phys(C.P, d, in.Ste, o);
+        C.eps = (float)ep;
+        if (ep < 1.0) {
+            const double k = d.K_default, cf = 1.75 / std::sqrt(o.ergun_c * ep * ep * ep);
+            C.Ac = (float)(ep * d.nu_l / (k * (1 - ep) * (1 - ep)));
+            C.Bc = (float)(ep * cf / (std::sqrt(k) * (1 - ep)));
+        }
+        const size_t pl = (size_t)C.G.plane;  // a multiple of 64 floats
+        C.f_off = b->f_len;
+        C.g_off = b->g_len;
+        C.fl_off = b->fl_len;
+        C.u_off = b->u_len;
+        b->f_len += dmrtk::FQ * pl;
+        b->g_len += 5 * pl;
+        b->fl_len += pl;
+        b->u_len += 2 * pl;
+        b->cells += (int64_t)in.grid.nx * in.grid.ny;
+    }
+    hipError_t e = hipGetDevice(&b->dev);
+    if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+
+    const size_t bytes_f = align256(b->f_len * 4), bytes_g = align256(b->g_len * 4);
+    const size_t bytes_fl = align256(b->fl_len * 4), bytes_u = align256(b->u_len * 4);
+    const size_t bytes_c = align256((size_t)ncav * sizeof(dmrtk::Cavity));
+    const size_t bytes_p = align256((size_t)2 * kCountBlocks * ncav * sizeof(long long));
+    const size_t total = 2 * (bytes_f + bytes_g + bytes_fl) + bytes_u + bytes_c + bytes_p;
+    e = hipMalloc(&b->base, total);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE,
+                         "hipMalloc(%zu): %s", total, hipGetErrorString(e)));
+    char* p = b->base;
+    auto take = [&](size_t n) {
+        char* r = p;
+        p += n;
+        return r;
+    };
+    for (int k = 0; k < 2; ++k) {
+        b->f[k] = (float*)take(bytes_f);
+        b->g[k] = (float*)take(bytes_g);
+        b->fl[k] = (float*)take(bytes_fl);
+    }
+    b->u = (float*)take(bytes_u);
+    b->dcav = (dmrtk::Cavity*)take(bytes_c);
+    b->partials = (long long*)take(bytes_p);
+    e = hipMemsetAsync(b->base, 0, total, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dcav, b->cav.data(), (size_t)ncav * sizeof(dmrtk::Cavity),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "upload: %s", hipGetErrorString(e)));
+    // initial state of every cavity: uniform T_init at rest
+    for (int c = 0; c < ncav; ++c) {
+        const dmrtk::Cavity& C = b->cav[c];
+        e = dmrtk::launch_load_state(C.G, C.P, nullptr, nullptr, nullptr, b->f[0] + C.f_off,
+                                     b->g[0] + C.g_off, b->fl[0] + C.fl_off, b->u + C.u_off,
+                                     b->u + C.u_off + C.G.plane, nullptr, nullptr, nullptr, true,
+                                     b->stream, C.eps, C.Ac, C.Bc);
+        if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "initial state: %s", hipGetErrorString(e)));
+    }
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "initial state: %s", hipGetErrorString(e)));
+    if ((rc = batch_layout(b, o.block_rows ? o.block_rows : 4, 0))) return bail(rc);
+    *out = b;
+    return DMRT_OK;
+}
+
+int dmrt_batch_step(dmrt_batch_t* b, int64_t n)
+{
+    if (!b) return fail(DMRT_EINVAL, "null handle");
+    if (n < 0) return fail(DMRT_EINVAL, "negative step count");
+    HIPCHK(hipSetDevice(b->dev));
+    return batch_step_impl(b, n);
+}
+
+int dmrt_batch_fields(dmrt_batch_t* b, int32_t i, float* T, float* ux, float* uy, float* fl)
+{
+    if (!b) return fail(DMRT_EINVAL, "null handle");
+    if (i < 0 || i >= b->ncav) return fail(DMRT_EINVAL, "cavity %d out of range", i);
+    HIPCHK(hipSetDevice(b->dev));
+    const dmrtk::Cavity& C = b->cav[i];
+    const size_t ncell = (size_t)C.G.nx * C.G.ny;
+    float* s = nullptr;
+    HIPCHK(hipMalloc(&s, 4 * ncell * sizeof(float)));
+    const int a = b->cur;
+    hipError_t e = dmrtk::launch_fields(C.G, b->g[a] + C.g_off, b->fl[a] + C.fl_off, b->u + C.u_off,
+                                        b->u + C.u_off + C.G.plane, true, s, b->stream);
+    float* dst[4] = {T, ux, uy, fl};
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        if (dst[k]) e = hipMemcpyAsync(dst[k], s + k * ncell, ncell * 4, hipMemcpyDefault, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(s);
+    if (e != hipSuccess) return fail(DMRT_EDEVICE, "fields: %s", hipGetErrorString(e));
+    return DMRT_OK;
+}
+
+int dmrt_batch_check(dmrt_batch_t* b, int64_t* liquid, int64_t* nonfinite)
+{
+    if (!b) return fail(DMRT_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(b->dev));
+    std::vector<long long> liq, bad;
+    int rc = batch_counts(b, liq, bad);
+    if (rc) return rc;
+    for (int c = 0; c < b->ncav; ++c) {
+        if (liquid) liquid[c] = liq[c];
+        if (nonfinite) nonfinite[c] = bad[c];
+    }
+    return DMRT_OK;
+}
+
+int dmrt_batch_set_launch(dmrt_batch_t* b, int32_t rows, int32_t blocks)
+{
+    if (!b) return fail(DMRT_EINVAL, "null handle");
+    if (rows != 4 && rows != 8) return fail(DMRT_EINVAL, "rows must be 4 or 8");
+    if (blocks < 0 || blocks % dmrtk::NXCD)
+        return fail(DMRT_EINVAL, "blocks must be 0 or a positive multiple of 8");
+    HIPCHK(hipSetDevice(b->dev));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return batch_layout(b, rows, blocks);
+}
+
+int dmrt_batch_get_launch(const dmrt_batch_t* b, int32_t* rows, int32_t* blocks)
+{
+    if (!b) return fail(DMRT_EINVAL, "null handle");
+    if (rows) *rows = b->rows;
+    if (blocks) *blocks = b->launch_blocks;
+    return DMRT_OK;
+}
+
+int dmrt_batch_tune(dmrt_batch_t* b, int32_t trial_steps, int32_t* rows, int32_t* blocks,
+                    double* ms_per_step)
+{
+    if (!b) return fail(DMRT_EINVAL, "null handle");
+    if (trial_steps < 1) return fail(DMRT_EINVAL, "trial_steps must be >= 1");
+    HIPCHK(hipSetDevice(b->dev));
+    // candidates: tile rows x (resident blocks, twice that, one block per tile)
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->dev));
+    struct Cand { int rows, blocks; };
+    std::vector<Cand> cands;
+    for (int r : {4, 8}) {
+        const int res = dmrtk::batch_blocks_per_cu(r) * ncu / dmrtk::NXCD * dmrtk::NXCD;
+        for (int nb : {res, 2 * res, 1 << 30}) cands.push_back({r, nb / dmrtk::NXCD * dmrtk::NXCD});
+    }
+    // snapshot of the current state (the trial steps overwrite both buffers)
+    const int a = b->cur;
+    const size_t nf = b->f_len * 4, ng = b->g_len * 4, nfl = b->fl_len * 4, nu = b->u_len * 4;
+    char* snap = nullptr;
+    HIPCHK(hipMalloc(&snap, nf + ng + nfl + nu));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto save = [&](bool restore) {
+        char* q = snap;
+        hipError_t r = hipSuccess;
+        const std::pair<char*, size_t> parts[4] = {{(char*)b->f[a], nf}, {(char*)b->g[a], ng},
+                                                   {(char*)b->fl[a], nfl}, {(char*)b->u, nu}};
+        for (const auto& pr : parts) {
+            if (r == hipSuccess)
+                r = restore ? hipMemcpyAsync(pr.first, q, pr.second, hipMemcpyDeviceToDevice, b->stream)
+                            : hipMemcpyAsync(q, pr.first, pr.second, hipMemcpyDeviceToDevice, b->stream);
+            q += pr.second;
+        }
+        return r;
+    };
+    if (e == hipSuccess) e = save(false);
+    const int keep_rows = b->rows, keep_blocks = b->blocks;
+    int best = -1, rc = DMRT_OK;
+    float best_ms = 0;
+    for (size_t k = 0; k < cands.size() && e == hipSuccess && rc == DMRT_OK; ++k) {
+        if ((rc = batch_layout(b, cands[k].rows, cands[k].blocks))) break;
+        b->cur = a;
+        // trial_steps untimed steps (the state moves past its first steps,
+        // which are not representative), then trial_steps timed ones
+        for (int s = 0; s < trial_steps && e == hipSuccess; ++s) {
+            e = dmrtk::launch_batch_step(batch_args(b, b->cur), b->rows, b->launch_blocks, b->stream);
+            b->cur = 1 - b->cur;
+        }
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int s = 0; s < trial_steps && e == hipSuccess; ++s) {
+            e = dmrtk::launch_batch_step(batch_args(b, b->cur), b->rows, b->launch_blocks, b->stream);
+            b->cur = 1 - b->cur;
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+            best = (int)k;
+            best_ms = ms;
+        }
+        b->cur = a;
+        if (e == hipSuccess) e = save(true);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(snap);
+    b->cur = a;
+    if (e != hipSuccess) rc = fail(DMRT_EDEVICE, "tune: %s", hipGetErrorString(e));
+    if (rc || best < 0) {
+        (void)batch_layout(b, keep_rows, keep_blocks);
+        return rc ? rc : fail(DMRT_EDEVICE, "tune: no candidate ran");
+    }
+    if ((rc = batch_layout(b, cands[best].rows, cands[best].blocks))) return rc;
+    if (rows) *rows = b->rows;
+    if (blocks) *blocks = b->launch_blocks;
+    if (ms_per_step) *ms_per_step = best_ms / trial_steps;
+    return DMRT_OK;
+}
+
+int dmrt_batch_get_derived(const dmrt_batch_t* b, int32_t i, dmrt_derived* out)
+{
+    if (!b || !out) return fail(DMRT_EINVAL, "null argument");
+    if (i < 0 || i >= b->ncav) return fail(DMRT_EINVAL, "cavity %d out of range", i);
+    *out = b->D[i];
+    return DMRT_OK;
+}
+
+int64_t dmrt_batch_cells(const dmrt_batch_t* b) { return b ? b->cells : fail(DMRT_EINVAL, "null handle"); }
+
+int64_t dmrt_batch_time(const dmrt_batch_t* b) { return b ? b->t : fail(DMRT_EINVAL, "null handle"); }
+
+int dmrt_batch_sync(dmrt_batch_t* b)
+{
+    if (!b) return fail(DMRT_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(b->dev));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return DMRT_OK;
+}
+
+void dmrt_batch_destroy(dmrt_batch_t* b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->dev);
+    if (b->base) (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    if (b->dtiles) (void)hipFree(b->dtiles);
+    if (b->base) (void)hipFree(b->base);
+    delete b;
+}
 
 }  // extern "C"

@@ -1,0 +1,131 @@
+// Batched step: many independent cavities of uneven size and parameters
+// advance together in one persistent launch per time step.  Every cavity
+// runs the same per-node step as a single lattice (dmrt_node.h), with its
+// own lattice constants and uniform porous fields.
+//
+// Tiles of 64 x rows nodes of all cavities form one list (cavity by
+// cavity, row-major inside a cavity).  The list is cut into eight
+// contiguous parts of about equal node count, one per die; block b works on
+// die b % 8 and strides through that die's part, so a die keeps whole
+// cavities (and their halo rows) in its own L2.
+#include "dmrt_node.h"
+
+namespace dmrtk {
+namespace {
+
+// The tile list and the cavity table do not change during a launch: they
+// are read word by word through the constant address space, so the uniform
+// loads become scalar loads and every per-cavity constant stays in scalar
+// registers.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized records only");
+    using cword = const __attribute__((address_space(4))) uint32_t;
+    cword* src = (cword*)p;
+    T v;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+    return v;
+}
+
+template <int TYB>
+__global__ __launch_bounds__(TX * TYB) void k_batch_step(BatchArgs a)
+{
+    __shared__ FlowStage<TX * TYB> S;
+    const int xcd = (int)(blockIdx.x & (NXCD - 1));
+    const int local = (int)(blockIdx.x >> 3), nloc = (int)(gridDim.x >> 3);
+    const int hi = a.die[xcd + 1];
+    int parity = 0;
+    for (int t = a.die[xcd] + local; t < hi; t += nloc, parity ^= 1) {
+        const int4 tile = load_uniform(a.tiles + t);
+        const Cavity C = load_uniform(a.cav + tile.x);
+        const Geom& G = C.G;
+        const Phys& P = C.P;
+        StepBufs B;
+        B.fin = a.fin + C.f_off;
+        B.fout = a.fout + C.f_off;
+        B.gin = a.gin + C.g_off;
+        B.gout = a.gout + C.g_off;
+        B.flin = a.flin + C.fl_off;
+        B.flout = a.flout + C.fl_off;
+        B.ux = a.u + C.u_off;
+        B.uy = a.u + C.u_off + G.plane;
+        B.eps = B.Ac = B.Bc = nullptr;
+        B.it_sum = B.it_max = nullptr;
+        Arrays<BufIO> A(G, B);
+        A.eps_u = C.eps;
+        A.Ac_u = C.Ac;
+        A.Bc_u = C.Bc;
+        const int x = tile.y + (int)threadIdx.x, y = tile.z + (int)threadIdx.y;
+        block_step<BufIO, true, false, true, TX * TYB>(G, P, B, A, x, y, x < G.nx && y < G.ny, S,
+                                                      parity);
+    }
+}
+
+// Per-cavity partial counts (blockIdx.y = cavity): liquid nodes (f_l > 0)
+// and non-finite values of f_l and g.  Padding columns hold zeros.
+__global__ __launch_bounds__(256) void k_batch_count(const Cavity* cav, const float* fl,
+                                                     const float* g, long long* partials)
+{
+    __shared__ long long red[2][4];
+    const Cavity& C = cav[blockIdx.y];
+    const long long n = C.G.plane, n5 = 5 * C.G.plane;
+    const float* flc = fl + C.fl_off;
+    const float* gc = g + C.g_off;
+    long long liq = 0, bad = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long i = i0; i < n; i += stride) {
+        const float v = flc[i];
+        liq += v > 0.0f;
+        bad += !isfinite(v);
+    }
+    for (long long i = i0; i < n5; i += stride) bad += !isfinite(gc[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        liq += __shfl_xor(liq, o, 64);
+        bad += __shfl_xor(bad, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = liq;
+        red[1][w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        long long v = 0;
+        for (int k = 0; k < 4; ++k) v += red[threadIdx.x][k];
+        partials[2 * ((long long)blockIdx.y * gridDim.x + blockIdx.x) + threadIdx.x] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_step(const BatchArgs& a, int rows, int blocks, hipStream_t s)
+{
+    if (rows == 8)
+        hipLaunchKernelGGL(k_batch_step<8>, dim3(blocks), dim3(TX, 8), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_batch_step<4>, dim3(blocks), dim3(TX, 4), 0, s, a);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int rows)
+{
+    int nb = 0;
+    hipError_t e = rows == 8
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<8>, TX * 8, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<4>, TX * 4, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t launch_batch_count(const Cavity* cav, int ncav, const float* fl, const float* g,
+                              long long* partials, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_count, dim3(nblk, ncav), dim3(256), 0, s, cav, fl, g, partials);
+    return hipGetLastError();
+}
+
+}  // namespace dmrtk

@@ -13,6 +13,10 @@ namespace dmrtk {
 constexpr int TX = 64;
 constexpr int TY = 4;   // block rows of the auxiliary kernels
 constexpr int NXCD = 8;  // MI355X: 8 accelerator dies, each with its own L2
+// Planes of an f array: the nine post-collision deviations f+_i - w_i and,
+// for liquid nodes, rho - 1 = their sum (what a melting neighbour restarts
+// from).
+constexpr int FQ = 10;
 
 // Uniform model constants of one run, in the form the kernels use them.
 struct Phys {
@@ -71,13 +75,49 @@ struct StepBufs {
 hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flow,
                        bool counted, hipStream_t s);
 
+// One cavity of a batch: its lattice, its model constants, its uniform
+// porous fields and the element offsets of its planes in the shared arenas.
+struct Cavity {
+    Geom G;
+    Phys P;
+    float eps, Ac, Bc, pad;
+    unsigned long long f_off, g_off, fl_off, u_off;
+};
+
+// Arguments of one batched step (buffers of the current and next state).
+struct BatchArgs {
+    const Cavity* __restrict__ cav;
+    const int4* __restrict__ tiles;  // (cavity, x0, y0, 0) per tile of 64 x rows nodes
+    int die[NXCD + 1];               // die d works on tiles [die[d], die[d + 1])
+    const float* fin;
+    float* fout;
+    const float* gin;
+    float* gout;
+    const float* flin;
+    float* flout;
+    float* u;
+};
+
+// Persistent batched step: `blocks` blocks (a multiple of 8) of 64 x rows
+// lanes; the blocks of die d walk that die's part of the tile list.
+hipError_t launch_batch_step(const BatchArgs& a, int rows, int blocks, hipStream_t s);
+// Blocks of 64 x rows lanes that fit on one compute unit at once.
+int batch_blocks_per_cu(int rows);
+// Per-cavity partial counts of liquid nodes (f_l > 0) and of non-finite f_l
+// and g values: partials[2 * (cavity * nblk + block) + {0, 1}].
+hipError_t launch_batch_count(const Cavity* cav, int ncav, const float* fl, const float* g,
+                              long long* partials, int nblk, hipStream_t s);
+
 // Load a pre-collision state (planar, row stride nx; any of f/g/fl may be
 // null) and store its post-collision populations into the current buffers.
+// eps/Ac/Bc may be null: the lattice then has the uniform values eps_u,
+// Ac_u, Bc_u.
 hipError_t launch_load_state(const Geom& G, const Phys& P, const float* f_pre,
                              const float* g_pre, const float* fl_pre, float* fcur,
                              float* gcur, float* flcur, float* ux, float* uy,
                              const float* eps, const float* Ac, const float* Bc,
-                             bool flow, hipStream_t s);
+                             bool flow, hipStream_t s, float eps_u = 0.0f, float Ac_u = 0.0f,
+                             float Bc_u = 0.0f);
 
 // T, ux, uy, f_l into out[4][ny][nx].
 hipError_t launch_fields(const Geom& G, const float* gcur, const float* flcur,

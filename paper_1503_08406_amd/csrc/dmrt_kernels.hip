@@ -23,7 +23,8 @@ __global__ __launch_bounds__(TX * TY) void k_load_state(Geom G, Phys P, const fl
                                                         const float* g_pre, const float* fl_pre,
                                                         float* fcur, float* gcur, float* flcur,
                                                         float* uxb, float* uyb, const float* epsb,
-                                                        const float* Ac, const float* Bc)
+                                                        const float* Acb, const float* Bcb,
+                                                        float eps_u, float Ac_u, float Bc_u)
 {
     int x, y;
     if (!tile_coords<TY>(G, x, y)) return;
@@ -42,15 +43,20 @@ __global__ __launch_bounds__(TX * TY) void k_load_state(Geom G, Phys P, const fl
     } else {
         fl = fminf(fmaxf((T - P.T_s) * P.inv_dTm, 0.0f), 1.0f);  // Eq. (42)
     }
-    const float eps = epsb[c];
+    const float eps = epsb ? epsb[c] : eps_u;
     float ux = 0.0f, uy = 0.0f;
     if (FLOW && fl > 0.0f) {
         float d[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) d[i] = f_pre ? f_pre[i * cp + ci] - w9(i) : 0.0f;
-        flow_collide(d, fl, eps, Ac[c], Bc[c], T, P, ux, uy);
+        flow_collide(d, fl, eps, Acb ? Acb[c] : Ac_u, Bcb ? Bcb[c] : Bc_u, T, P, ux, uy);
+        float r = 0.0f;  // rho - 1, summed in population order
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fcur[i * pl + c] = d[i];
+        for (int i = 0; i < 9; ++i) {
+            fcur[i * pl + c] = d[i];
+            r += d[i];
+        }
+        fcur[9 * pl + c] = r;
         uxb[c] = ux;
         uyb[c] = uy;
     }
@@ -204,15 +210,16 @@ inline dim3 tile_grid(const Geom& G) { return dim3(tile_blocks(G, TY)); }
 hipError_t launch_load_state(const Geom& G, const Phys& P, const float* f_pre, const float* g_pre,
                              const float* fl_pre, float* fcur, float* gcur, float* flcur,
                              float* ux, float* uy, const float* eps, const float* Ac,
-                             const float* Bc, bool flow, hipStream_t s)
+                             const float* Bc, bool flow, hipStream_t s, float eps_u, float Ac_u,
+                             float Bc_u)
 {
     const dim3 blk(TX, TY), grd = tile_grid(G);
     if (flow)
         hipLaunchKernelGGL((k_load_state<true>), grd, blk, 0, s, G, P, f_pre, g_pre, fl_pre, fcur,
-                           gcur, flcur, ux, uy, eps, Ac, Bc);
+                           gcur, flcur, ux, uy, eps, Ac, Bc, eps_u, Ac_u, Bc_u);
     else
         hipLaunchKernelGGL((k_load_state<false>), grd, blk, 0, s, G, P, f_pre, g_pre, fl_pre,
-                           fcur, gcur, flcur, ux, uy, eps, Ac, Bc);
+                           fcur, gcur, flcur, ux, uy, eps, Ac, Bc, eps_u, Ac_u, Bc_u);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdmrt.so")
+LIB_PATH = os.environ.get("DMRT_LIB_PATH") or os.path.join(_HERE, "libdmrt.so")
 
 DMRT_OK, DMRT_EINVAL, DMRT_ENOMEM, DMRT_EDEVICE, DMRT_ENONFINITE, DMRT_ESIZE = 0, -1, -2, -3, -4, -5
 PERIODIC, WALL_T, WALL_ADIABATIC = 0, 1, 2
@@ -38,6 +38,11 @@ class Opts(C.Structure):
               [("fl_maxit", C.c_int32), ("convective", C.c_int32), ("check_every", C.c_int32),
                ("graph_steps", C.c_int32), ("block_rows", C.c_int32), ("cells_per_lane", C.c_int32),
                ("stream", C.c_void_p)]
+
+
+class Cavity(C.Structure):
+    _fields_ = [("grid", Grid), ("bc", BC), ("eps", C.c_double), ("Ra", C.c_double),
+                ("Da", C.c_double), ("Pr", C.c_double), ("Ste", C.c_double)]
 
 
 class Derived(C.Structure):
@@ -93,6 +98,19 @@ def _load():
         "dmrt_sync": (C.c_int, [P]),
         "dmrt_destroy": (None, [P]),
         "dmrt_last_error": (C.c_char_p, []),
+        "dmrt_batch_create": (C.c_int, [C.c_int32, C.POINTER(Cavity), C.POINTER(Opts), C.POINTER(P)]),
+        "dmrt_batch_step": (C.c_int, [P, C.c_int64]),
+        "dmrt_batch_fields": (C.c_int, [P, C.c_int32, VP, VP, VP, VP]),
+        "dmrt_batch_check": (C.c_int, [P, VP, VP]),
+        "dmrt_batch_set_launch": (C.c_int, [P, C.c_int32, C.c_int32]),
+        "dmrt_batch_get_launch": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "dmrt_batch_tune": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_double)]),
+        "dmrt_batch_get_derived": (C.c_int, [P, C.c_int32, C.POINTER(Derived)]),
+        "dmrt_batch_cells": (C.c_int64, [P]),
+        "dmrt_batch_time": (C.c_int64, [P]),
+        "dmrt_batch_sync": (C.c_int, [P]),
+        "dmrt_batch_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -259,3 +277,123 @@ class Solver:
     def load(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         _check(_lib.dmrt_load(self._h, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
+
+
+class BatchSolver:
+    """Many independent cavities advanced together by one launch per step.
+    `cavities` is a list of dicts with nx, ny, bc_kind, T_wall, eps (a
+    scalar), Ra, Da, Pr, Ste and optionally H; keyword arguments are solver
+    options shared by all cavities."""
+
+    def __init__(self, cavities, stream=None, **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the dmrt solver needs a ROCm GPU")
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        o = make_opts(**opts)
+        o.stream = C.c_void_p(self.stream.cuda_stream)
+        n = len(cavities)
+        arr = (Cavity * n)()
+        for i, c in enumerate(cavities):
+            a = arr[i]
+            a.grid = Grid(int(c["nx"]), int(c["ny"]), float(c.get("H", 0.0)))
+            for k in range(4):
+                a.bc.kind[k] = int(c["bc_kind"][k])
+                a.bc.T_wall[k] = float(c["T_wall"][k])
+            a.eps, a.Ra, a.Da, a.Pr, a.Ste = (float(c[k]) for k in ("eps", "Ra", "Da", "Pr", "Ste"))
+        self.shapes = [(int(c["ny"]), int(c["nx"])) for c in cavities]
+        h = C.c_void_p()
+        _check(_lib.dmrt_batch_create(n, arr, C.byref(o), C.byref(h)))
+        self._h = h
+        self.ncav = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dmrt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def time(self):
+        return _lib.dmrt_batch_time(self._h)
+
+    @property
+    def cells(self):
+        return _lib.dmrt_batch_cells(self._h)
+
+    def step(self, n=1):
+        _check(_lib.dmrt_batch_step(self._h, int(n)))
+
+    def sync(self):
+        _check(_lib.dmrt_batch_sync(self._h))
+
+    def fields(self, i):
+        if not 0 <= i < self.ncav:
+            raise IndexError("cavity %d out of range" % i)
+        out = {k: np.zeros(self.shapes[i], np.float32) for k in ("T", "ux", "uy", "fl")}
+        _check(_lib.dmrt_batch_fields(self._h, int(i), _ptr(out["T"]), _ptr(out["ux"]),
+                                      _ptr(out["uy"]), _ptr(out["fl"])))
+        return out
+
+    def check(self):
+        """Per-cavity (liquid node count, non-finite value count)."""
+        liq = np.zeros(self.ncav, np.int64)
+        bad = np.zeros(self.ncav, np.int64)
+        _check(_lib.dmrt_batch_check(self._h, liq.ctypes.data_as(C.c_void_p),
+                                     bad.ctypes.data_as(C.c_void_p)))
+        return liq, bad
+
+    def derived(self, i):
+        d = Derived()
+        _check(_lib.dmrt_batch_get_derived(self._h, int(i), C.byref(d)))
+        return {n: getattr(d, n) for n, _ in Derived._fields_}
+
+    def set_launch(self, rows, blocks=0):
+        _check(_lib.dmrt_batch_set_launch(self._h, int(rows), int(blocks)))
+
+    def launch(self):
+        r, b = C.c_int32(), C.c_int32()
+        _check(_lib.dmrt_batch_get_launch(self._h, C.byref(r), C.byref(b)))
+        return r.value, b.value
+
+    def tune(self, trial_steps=10, cache=None):
+        """Pick the fastest launch shape by timing trial steps on a copy of
+        the state (the library's tuner; results are unchanged).  With `cache`
+        (a JSON file path) the choice is stored under a key made of the device
+        name and the cavity sizes, and later batches of the same sizes reuse
+        it without timing.  Returns (rows, blocks, ms_per_step or None)."""
+        import hashlib
+        import json
+        key = None
+        if cache:
+            dev = self.torch.cuda.get_device_name(self.torch.cuda.current_device())
+            sizes = hashlib.sha1(repr(self.shapes).encode()).hexdigest()[:16]
+            key = "%s|%d|%s" % (dev, self.ncav, sizes)
+            try:
+                with open(cache) as fh:
+                    hit = json.load(fh).get(key)
+            except (OSError, ValueError):
+                hit = None
+            if hit:
+                self.set_launch(hit["rows"], hit["blocks"])
+                return hit["rows"], hit["blocks"], None
+        r, b, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(_lib.dmrt_batch_tune(self._h, int(trial_steps), C.byref(r), C.byref(b), C.byref(ms)))
+        if key:
+            try:
+                with open(cache) as fh:
+                    db = json.load(fh)
+            except (OSError, ValueError):
+                db = {}
+            db[key] = {"rows": r.value, "blocks": b.value, "ms_per_step": ms.value}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(db, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return r.value, b.value, ms.value

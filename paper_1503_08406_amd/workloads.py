@@ -14,6 +14,8 @@ Workloads (the paper's three validation problems restated at new sizes):
   corner            Sec. 4.2 -- 256x256, cold left and bottom walls
   cavity            Sec. 4.3 -- 1024x1024 convection melting, seeded
                     log-normal permeability perturbation (sigma 0.1)
+  cavity_batch      many Sec. 4.3 cavities of seeded uneven sizes and
+                    parameters, uniform porous fields per cavity
 """
 import math
 
@@ -78,6 +80,40 @@ def cavity(nx=1024, ny=1024, steps=100000, Ra=1e6, Da=1e-4, Pr=1.0, Ste=1.0,
                      [1.0, 0.0, 0.0, 0.0], Ra=Ra, Da=Da, Pr=Pr, Ste=Ste, eps=porosity,
                      K=K, steps=steps, T_init=T_init, T_s=THETA_M_CAVITY - 0.02,
                      T_l=THETA_M_CAVITY + 0.02, convective=1)
+
+
+CAVITY_BATCH_OPTS = dict(T_init=0.0, T_s=THETA_M_CAVITY - 0.02, T_l=THETA_M_CAVITY + 0.02,
+                         convective=1)
+
+
+def cavity_batch(n=512, seed=4, size_lo=64, size_hi=512, steps=10000):
+    """Independent Sec. 4.3 cavities (hot left wall, cold right wall,
+    adiabatic top and bottom, initially solid at theta = 0) with seeded
+    uneven sizes and parameters: nx, ny iid integers in [size_lo, size_hi],
+    Ra = 10^U(4, 6), Da = 10^U(-5, -2), porosity U(0.3, 0.9) (rounded to
+    float32), Ste U(0.1, 2), Pr = 1, H = ny; each cavity has uniform porous
+    fields (K = Da H^2, F_eps from the Ergun relation).  Returns (cavities,
+    shared options, steps)."""
+    rng = np.random.default_rng(seed)
+    nx = rng.integers(size_lo, size_hi + 1, n)
+    ny = rng.integers(size_lo, size_hi + 1, n)
+    Ra = 10.0 ** rng.uniform(4.0, 6.0, n)
+    Da = 10.0 ** rng.uniform(-5.0, -2.0, n)
+    eps = rng.uniform(0.3, 0.9, n).astype(np.float32).astype(np.float64)
+    Ste = rng.uniform(0.1, 2.0, n)
+    cavs = [dict(nx=int(nx[i]), ny=int(ny[i]), H=0.0,
+                 bc_kind=[WALL_T, WALL_T, WALL_ADIABATIC, WALL_ADIABATIC],
+                 T_wall=[1.0, 0.0, 0.0, 0.0], eps=float(eps[i]), Ra=float(Ra[i]),
+                 Da=float(Da[i]), Pr=1.0, Ste=float(Ste[i])) for i in range(n)]
+    return cavs, dict(CAVITY_BATCH_OPTS), int(steps)
+
+
+def batch_member(cav, opts, steps=0):
+    """One cavity of a batch as a single-lattice workload (uniform porosity
+    array, K and F_eps left to the solver's defaults)."""
+    return make_case("batch_member", cav["nx"], cav["ny"], cav["bc_kind"], cav["T_wall"],
+                     Ra=cav["Ra"], Da=cav["Da"], Pr=cav["Pr"], Ste=cav["Ste"], eps=cav["eps"],
+                     steps=steps, H=cav.get("H", 0.0), **opts)
 
 
 def periodic_box(nx, ny, T, fl_phase="liquid", Ra=1e5, Da=1e-2, Pr=1.0, Ste=1.0,

@@ -10,8 +10,11 @@ nothing here comes from the HIP path.
                          hot wall and on sampled rows.
   cavity_1024_long.npz   the same workload over its full 100000 steps, with
                          snapshots after 20000, 50000 and 100000 steps.
+  batch_512_smallest.npz the three smallest cavities of the 512-cavity batch
+                         (seed 4), each over the batch's 10000 steps: T, u,
+                         f_l in full.
 
-Usage: python tests/golden/make_golden.py [corner|cavity ...]
+Usage: python tests/golden/make_golden.py [corner|cavity|cavity_long|batch ...]
 """
 import os
 import sys
@@ -110,6 +113,18 @@ def cavity_long():
         out["liquid_beyond_strip_%d" % n] = float(F["fl"][:, LONG_STRIP:].max())
         print("cavity_long: step %d (%.0f s)" % (n, time.time() - t), flush=True)
         np.savez_compressed(os.path.join(HERE, "cavity_1024_long.npz"), **out)
+
+
+def batch():
+    cavs, opts, steps = W.cavity_batch()
+    area = [c["nx"] * c["ny"] for c in cavs]
+    index = sorted(range(len(cavs)), key=lambda i: (area[i], i))[:3]
+    out = dict(steps=steps, index=np.array(index))
+    for k, i in enumerate(index):
+        F = run(W.batch_member(cavs[i], opts), steps)
+        for n in ("T", "ux", "uy", "fl"):
+            out["%s_%d" % (n, k)] = F[n]
+    np.savez_compressed(os.path.join(HERE, "batch_512_smallest.npz"), **out)
 
 
 if __name__ == "__main__":

@@ -117,3 +117,49 @@ def test_opts_defaults_are_the_papers():
     o = dmrt.default_opts()
     assert (o.varpi, o.s_e, o.s_eps, o.s_q, o.zeta_e, o.zeta_nu, o.Ma, o.J, o.ergun_c) == \
         (-2.0, 1.1, 1.1, 1.2, 1.5, 1.5, 0.1, 1.0, 175.0)
+
+
+@pytest.mark.parametrize("what", ["empty", "eps", "eps_zero", "bc", "Pr", "rows"])
+def test_batch_create_rejects_bad_arguments_without_device(what):
+    """Batch creation validates every cavity before touching the device and
+    names the first bad one."""
+    from paper_1503_08406_amd import dmrt
+    lib = dmrt.lib()
+    g, bc, o = _args()
+    cav = (dmrt.Cavity * 3)()
+    for c in cav:
+        c.grid = g
+        c.bc = bc
+        c.eps, c.Ra, c.Da, c.Pr, c.Ste = 0.5, 1e5, 1e-3, 1.0, 1.0
+    n = 3
+    if what == "empty":
+        n = 0
+    elif what == "eps":
+        cav[2].eps = 1.2
+    elif what == "eps_zero":
+        cav[1].eps = 0.0
+    elif what == "bc":
+        cav[1].bc.kind[2] = 0
+    elif what == "Pr":
+        cav[2].Pr = -1.0
+    elif what == "rows":
+        o.block_rows = 6
+    h = C.c_void_p()
+    rc = lib.dmrt_batch_create(n, cav, C.byref(o), C.byref(h))
+    assert rc == dmrt.DMRT_EINVAL and not h.value
+    msg = lib.dmrt_last_error().decode()
+    if what in ("eps", "Pr"):
+        assert "cavity 2" in msg, msg
+    if what in ("eps_zero", "bc"):
+        assert "cavity 1" in msg, msg
+
+
+def test_batch_calls_reject_null_handles():
+    from paper_1503_08406_amd import dmrt
+    lib = dmrt.lib()
+    assert lib.dmrt_batch_step(None, 1) == dmrt.DMRT_EINVAL
+    assert lib.dmrt_batch_fields(None, 0, None, None, None, None) == dmrt.DMRT_EINVAL
+    assert lib.dmrt_batch_check(None, None, None) == dmrt.DMRT_EINVAL
+    assert lib.dmrt_batch_tune(None, 1, None, None, None) == dmrt.DMRT_EINVAL
+    assert lib.dmrt_batch_set_launch(None, 4, 0) == dmrt.DMRT_EINVAL
+    lib.dmrt_batch_destroy(None)
