@@ -769,11 +769,22 @@ int batch_layout(dmrt_batch* b, int rows, int blocks)
     std::vector<long long> w;
     for (int c = 0; c < b->ncav; ++c) {
         const Geom& G = b->cav[c].G;
-        for (int y0 = 0; y0 < G.ny; y0 += rows)
-            for (int x0 = 0; x0 < G.nx; x0 += dmrtk::TX) {
-                tl.push_back(make_int4(c, x0, y0, 0));
-                w.push_back((long long)std::min(dmrtk::TX, G.nx - x0) * std::min(rows, G.ny - y0));
+        // 64-wide tiles, except a last column chunk of 1-32 nodes, which is
+        // covered by 32-wide tiles twice as tall (half the idle lanes)
+        const int rem = G.nx % dmrtk::TX;
+        const bool narrow = rem > 0 && rem <= dmrtk::TX / 2;
+        const int xw = narrow ? G.nx - rem : G.nx;  // end of the wide tiles
+        for (int yb = 0; yb < G.ny; yb += 2 * rows) {
+            for (int y0 = yb; y0 < std::min(yb + 2 * rows, G.ny); y0 += rows)
+                for (int x0 = 0; x0 < xw; x0 += dmrtk::TX) {
+                    tl.push_back(make_int4(c, x0, y0, 0));
+                    w.push_back((long long)std::min(dmrtk::TX, G.nx - x0) * std::min(rows, G.ny - y0));
+                }
+            if (narrow) {
+                tl.push_back(make_int4(c, xw, yb, 1));
+                w.push_back((long long)rem * std::min(2 * rows, G.ny - yb));
             }
+        }
     }
     const int nt = (int)tl.size();
     long long total = 0;

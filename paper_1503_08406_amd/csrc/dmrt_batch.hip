@@ -3,8 +3,9 @@
 // runs the same per-node step as a single lattice (dmrt_node.h), with its
 // own lattice constants and uniform porous fields.
 //
-// Tiles of 64 x rows nodes of all cavities form one list (cavity by
-// cavity, row-major inside a cavity).  The list is cut into eight
+// Tiles of all cavities form one list (cavity by cavity, in memory order
+// inside a cavity): 64 x rows nodes, and 32 x 2*rows nodes where a
+// cavity's last columns are no more than 32 wide.  The list is cut into eight
 // contiguous parts of about equal node count, one per die; block b works on
 // die b % 8 and strides through that die's part, so a die keeps whole
 // cavities (and their halo rows) in its own L2.
@@ -58,7 +59,12 @@ __global__ __launch_bounds__(TX * TYB) void k_batch_step(BatchArgs a)
         A.eps_u = C.eps;
         A.Ac_u = C.Ac;
         A.Bc_u = C.Bc;
-        const int x = tile.y + (int)threadIdx.x, y = tile.z + (int)threadIdx.y;
+        // a wide tile is 64 x TYB nodes (a wavefront per row); a narrow one
+        // 32 x 2*TYB (a wavefront per two rows), for a cavity's last 1-32 columns
+        const int lane = (int)threadIdx.x, w = (int)threadIdx.y;
+        const bool narrow = tile.w != 0;
+        const int x = tile.y + (narrow ? (lane & 31) : lane);
+        const int y = tile.z + (narrow ? 2 * w + (lane >> 5) : w);
         block_step<BufIO, true, false, true, TX * TYB>(G, P, B, A, x, y, x < G.nx && y < G.ny, S,
                                                       parity);
     }

@@ -87,7 +87,8 @@ struct Cavity {
 // Arguments of one batched step (buffers of the current and next state).
 struct BatchArgs {
     const Cavity* __restrict__ cav;
-    const int4* __restrict__ tiles;  // (cavity, x0, y0, 0) per tile of 64 x rows nodes
+    const int4* __restrict__ tiles;  // (cavity, x0, y0, narrow): 64 x rows nodes, or
+                                     // 32 x 2*rows nodes when narrow != 0
     int die[NXCD + 1];               // die d works on tiles [die[d], die[d + 1])
     const float* fin;
     float* fout;

@@ -26,7 +26,8 @@ def _say(*a):
 
 
 def _small_batch():
-    """Six cavities: ragged sizes (one and several 64-wide tiles, ragged y),
+    """Six cavities: ragged sizes (one and several 64-wide tiles, last column
+    chunks wider and narrower than 32, a cavity narrower than 32, ragged y),
     C4-like parameters, one clear-fluid cavity (eps = 1) and one periodic in
     y; initial temperature just below melting so fronts and flow develop."""
     cavs, opts, _ = W.cavity_batch(n=6, seed=11, size_lo=20, size_hi=140)
@@ -34,6 +35,7 @@ def _small_batch():
     cavs[1].update(nx=130, ny=67)
     cavs[2].update(eps=1.0)
     cavs[3].update(nx=65, ny=9, H=64.0, Ra=2e4, bc_kind=[1, 1, 0, 0])
+    cavs[4].update(nx=27, ny=50)  # narrower than half a tile
     opts["T_init"] = W.THETA_M_CAVITY - 0.05
     return cavs, opts
 
@@ -106,7 +108,7 @@ def test_batch_matches_oracle():
     cavs, opts = _small_batch()
     b = BatchSolver(cavs, **opts)
     b.step(400)
-    for i in (0, 2, 3, 5):
+    for i in (0, 2, 3, 4, 5):
         _say("oracle", i)
         o = oracle_from_case(W.batch_member(cavs[i], opts))
         o.step(400)
