@@ -10,6 +10,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+# DMRT_LIB_PATH selects another build of the same library (for timing two
+# builds against each other); by default the in-tree build is loaded.
 LIB_PATH = os.environ.get("DMRT_LIB_PATH") or os.path.join(_HERE, "libdmrt.so")
 
 DMRT_OK, DMRT_EINVAL, DMRT_ENOMEM, DMRT_EDEVICE, DMRT_ENONFINITE, DMRT_ESIZE = 0, -1, -2, -3, -4, -5
