@@ -176,6 +176,28 @@ int64_t dmrt_state_bytes(const dmrt_t *h);
 int dmrt_save(dmrt_t *h, void *buf, size_t cap);
 int dmrt_load(dmrt_t *h, const void *buf, size_t n);
 
+/* Replace the porous fields (same meaning as in dmrt_create; K and Feps may
+ * be NULL).  The state is kept; a recorded run is discarded. */
+int dmrt_set_porous(dmrt_t *h, const float *eps, const float *K, const float *Feps);
+
+/* Differentiation of a run (NEXT row f2: the discrete adjoint of the step).
+ * dmrt_record advances n >= 1 steps like dmrt_step and keeps what the
+ * adjoint needs: the state every S = ceil(sqrt(n)) steps (checkpoints), plus
+ * room for one segment of S states that the adjoint recomputes.  Needs
+ * uniform sigma and tau_T (sigma_s == sigma_l, alpha_ratio == 1).
+ * dmrt_adjoint then returns, for a loss L of the fields at the end of the
+ * recorded run with adjoints dL_dT and dL_dfl (nx*ny each; NULL = 0), the
+ * gradients dL/dlog K and dL/deps per cell (nx*ny each; NULL = not wanted),
+ * K being the permeability at f_l = 1 and Feps held fixed when it was given
+ * (otherwise it follows eps through Eq. 6).  The enthalpy update is
+ * differentiated at its converged fixed point (zero derivative where f_l is
+ * clamped to 0 or 1); the flow mask and the liquid/solid status of pull
+ * sources are held fixed; |v| has the subgradient 0 at v = 0.  The state of
+ * the handle is not changed. */
+int dmrt_record(dmrt_t *h, int64_t n);
+int dmrt_adjoint(dmrt_t *h, const float *dL_dT, const float *dL_dfl, float *grad_logK,
+                 float *grad_eps);
+
 /* Time steps taken so far. */
 int64_t dmrt_time(const dmrt_t *h);
 

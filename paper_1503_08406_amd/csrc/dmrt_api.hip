@@ -64,6 +64,13 @@ struct dmrt {
     size_t scratch_bytes = 0;
     int *it_sum = nullptr, *it_max = nullptr;
     hipGraphExec_t graph[2]{};
+    double ergun_c = 175.0;
+    bool feps_given = false;
+    // recorded run for the adjoint: checkpoints every rec_S steps, the ring
+    // of states of one segment, the adjoint buffers
+    int64_t rec_n = 0, rec_S = 0;
+    char* rec_base = nullptr;
+    float *ckpt = nullptr, *ring = nullptr, *ls = nullptr, *la = nullptr, *ga = nullptr;
 };
 
 namespace {
@@ -335,6 +342,57 @@ int diag_impl(dmrt* h, dmrt_diag_t* out)
     return DMRT_OK;
 }
 
+// Porosity and drag-coefficient planes (pitched) from the caller's per-cell
+// eps, K, Feps (K NULL: Da H^2; Feps NULL: the Ergun relation of Eq. 6).
+int porous_planes(dmrt* h, const float* eps, const float* K, const float* Feps,
+                  std::vector<float>& pe, std::vector<float>& pa, std::vector<float>& pb)
+{
+    const Geom& G = h->G;
+    const size_t nx = (size_t)G.nx, ny = (size_t)G.ny, pitch = (size_t)G.pitch;
+    const size_t ncell = nx * ny;
+    std::vector<float> he(ncell), hk, hf;
+    int rc = copy_in(he.data(), eps, ncell * sizeof(float), h->stream);
+    if (rc) return rc;
+    if (K) {
+        hk.resize(ncell);
+        if ((rc = copy_in(hk.data(), K, ncell * sizeof(float), h->stream))) return rc;
+    }
+    if (Feps) {
+        hf.resize(ncell);
+        if ((rc = copy_in(hf.data(), Feps, ncell * sizeof(float), h->stream))) return rc;
+    }
+    const size_t pcell = (size_t)G.plane;
+    pe.assign(pcell, 1.0f);
+    pa.assign(pcell, 0.0f);
+    pb.assign(pcell, 0.0f);
+    for (size_t y = 0; y < ny; ++y)
+        for (size_t x = 0; x < nx; ++x) {
+            const size_t i = y * nx + x, j = y * pitch + x;
+            const double ep = he[i];
+            if (!(ep > 0.0 && ep <= 1.0))
+                return fail(DMRT_EINVAL, "eps[%zu] = %g outside (0, 1]", i, ep);
+            const double k = K ? (double)hk[i] : h->D.K_default;
+            if (!(k > 0) || !std::isfinite(k)) return fail(DMRT_EINVAL, "K[%zu] = %g must be > 0", i, k);
+            const double cf = Feps ? (double)hf[i] : 1.75 / std::sqrt(h->ergun_c * ep * ep * ep);
+            if (!(cf >= 0) || !std::isfinite(cf))
+                return fail(DMRT_EINVAL, "Feps[%zu] = %g must be finite and >= 0", i, cf);
+            pe[j] = (float)ep;
+            if (ep < 1.0) {  // eps = 1: clear fluid, no porous drag
+                pa[j] = (float)(ep * h->D.nu_l / (k * (1 - ep) * (1 - ep)));
+                pb[j] = (float)(ep * cf / (std::sqrt(k) * (1 - ep)));
+            }
+        }
+    return DMRT_OK;
+}
+
+void drop_recording(dmrt* h)
+{
+    if (h->rec_base) (void)hipFree(h->rec_base);
+    h->rec_base = nullptr;
+    h->ckpt = h->ring = h->ls = h->la = h->ga = nullptr;
+    h->rec_n = h->rec_S = 0;
+}
+
 int check_finite(dmrt* h)
 {
     dmrt_diag_t d;
@@ -427,36 +485,11 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
 
     // Inputs: stage through host memory, validate, derive the drag coefficients.
-    const size_t ncell = (size_t)nx * ny;
-    std::vector<float> he(ncell), hk, hf;
-    if ((rc = copy_in(he.data(), eps, ncell * sizeof(float), h->stream))) return bail(rc);
-    if (K) {
-        hk.resize(ncell);
-        if ((rc = copy_in(hk.data(), K, ncell * sizeof(float), h->stream))) return bail(rc);
-    }
-    if (Feps) {
-        hf.resize(ncell);
-        if ((rc = copy_in(hf.data(), Feps, ncell * sizeof(float), h->stream))) return bail(rc);
-    }
+    h->ergun_c = o.ergun_c;
+    h->feps_given = Feps != nullptr;
     const size_t pcell = (size_t)G.plane;
-    std::vector<float> pe(pcell, 1.0f), pa(pcell, 0.0f), pb(pcell, 0.0f);
-    for (long long y = 0; y < ny; ++y)
-        for (long long x = 0; x < nx; ++x) {
-            const size_t i = (size_t)(y * nx + x), j = (size_t)(y * pitch + x);
-            const double ep = he[i];
-            if (!(ep > 0.0 && ep <= 1.0))
-                return bail(fail(DMRT_EINVAL, "eps[%zu] = %g outside (0, 1]", i, ep));
-            const double k = K ? (double)hk[i] : d.K_default;
-            if (!(k > 0)) return bail(fail(DMRT_EINVAL, "K[%zu] = %g must be > 0", i, k));
-            const double cf = Feps ? (double)hf[i] : 1.75 / std::sqrt(o.ergun_c * ep * ep * ep);
-            if (!(cf >= 0) || !std::isfinite(cf))
-                return bail(fail(DMRT_EINVAL, "Feps[%zu] = %g must be finite and >= 0", i, cf));
-            pe[j] = (float)ep;
-            if (ep < 1.0) {  // eps = 1: clear fluid, no porous drag
-                pa[j] = (float)(ep * d.nu_l / (k * (1 - ep) * (1 - ep)));
-                pb[j] = (float)(ep * cf / (std::sqrt(k) * (1 - ep)));
-            }
-        }
+    std::vector<float> pe, pa, pb;
+    if ((rc = porous_planes(h, eps, K, Feps, pe, pa, pb))) return bail(rc);
 
     // Device memory: one allocation, 256-byte aligned sub-arrays.
     const size_t plane_b = align256(pcell * sizeof(float));
@@ -688,6 +721,161 @@ int dmrt_load(dmrt_t* h, const void* buf, size_t n)
     return DMRT_OK;
 }
 
+int dmrt_set_porous(dmrt_t* h, const float* eps, const float* K, const float* Feps)
+{
+    if (!h || !eps) return fail(DMRT_EINVAL, "handle and eps are required");
+    HIPCHK(hipSetDevice(h->dev));
+    std::vector<float> pe, pa, pb;
+    int rc = porous_planes(h, eps, K, Feps, pe, pa, pb);
+    if (rc) return rc;
+    const size_t n = (size_t)h->G.plane * sizeof(float);
+    HIPCHK(hipMemcpyAsync(h->eps, pe.data(), n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->Ac, pa.data(), n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->Bc, pb.data(), n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->feps_given = Feps != nullptr;
+    drop_recording(h);
+    return DMRT_OK;
+}
+
+int dmrt_record(dmrt_t* h, int64_t n)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    if (n < 1) return fail(DMRT_EINVAL, "record at least one step");
+    if (h->P.dsig != 0.0f || !h->P.zeta_uniform)
+        return fail(DMRT_EINVAL, "the adjoint needs uniform sigma and tau_T (sigma_s == sigma_l, alpha_ratio == 1)");
+    HIPCHK(hipSetDevice(h->dev));
+    drop_recording(h);
+    int64_t S = 1;
+    while (S * S < n) ++S;
+    const int64_t C = (n + S - 1) / S;
+    const size_t pl = (size_t)h->G.plane, sb = (size_t)dmrtk::ADJ_STATE * pl;
+    const size_t total = ((size_t)C * sb + (size_t)(S + 1) * sb +
+                          (size_t)(dmrtk::ADJ_LS + dmrtk::ADJ_LA + dmrtk::ADJ_GA) * pl) * sizeof(float);
+    hipError_t e = hipMalloc(&h->rec_base, total);
+    if (e != hipSuccess) {
+        h->rec_base = nullptr;
+        return fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE, "hipMalloc(%zu): %s", total,
+                    hipGetErrorString(e));
+    }
+    float* p = (float*)h->rec_base;
+    h->ckpt = p;
+    h->ring = p + (size_t)C * sb;
+    h->ls = h->ring + (size_t)(S + 1) * sb;
+    h->la = h->ls + (size_t)dmrtk::ADJ_LS * pl;
+    h->ga = h->la + (size_t)dmrtk::ADJ_LA * pl;
+    const size_t fb = (size_t)dmrtk::FQ * pl * sizeof(float), pb = pl * sizeof(float);
+    for (int64_t c = 0; c < C; ++c) {
+        float* q = h->ckpt + (size_t)c * sb;
+        const int a = h->cur;
+        HIPCHK(hipMemcpyAsync(q, h->f[a], fb, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(q + dmrtk::FQ * pl, h->g[a], 5 * pb, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(q + (dmrtk::FQ + 5) * pl, h->fl[a], pb, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(q + (dmrtk::FQ + 6) * pl, h->ux, 2 * pb, hipMemcpyDeviceToDevice, h->stream));
+        int rc = dmrt_step(h, std::min(S, n - c * S));
+        if (rc) {
+            drop_recording(h);
+            return rc;
+        }
+    }
+    h->rec_n = n;
+    h->rec_S = S;
+    return DMRT_OK;
+}
+
+int dmrt_adjoint(dmrt_t* h, const float* dL_dT, const float* dL_dfl, float* grad_logK,
+                 float* grad_eps)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    if (!h->rec_n) return fail(DMRT_EINVAL, "no recorded run (call dmrt_record first)");
+    HIPCHK(hipSetDevice(h->dev));
+    const Geom& G = h->G;
+    const size_t pl = (size_t)G.plane, sb = (size_t)dmrtk::ADJ_STATE * pl;
+    const size_t pitch_b = (size_t)G.pitch * sizeof(float), row_b = (size_t)G.nx * sizeof(float);
+    const int64_t n = h->rec_n, S = h->rec_S, C = (n + S - 1) / S;
+    // terminal adjoint: T = sum of g+, so dL/dg+_i = dL/dT for every i
+    HIPCHK(hipMemsetAsync(h->ls, 0, (size_t)(dmrtk::ADJ_LS + dmrtk::ADJ_LA + dmrtk::ADJ_GA) * pl * sizeof(float),
+                          h->stream));
+    for (int i = 0; i < 5; ++i)
+        if (dL_dT)
+            HIPCHK(hipMemcpy2DAsync(h->ls + (size_t)(10 + i) * pl, pitch_b, dL_dT, row_b, row_b, G.ny,
+                                    hipMemcpyDefault, h->stream));
+    if (dL_dfl)
+        HIPCHK(hipMemcpy2DAsync(h->ls + 15 * pl, pitch_b, dL_dfl, row_b, row_b, G.ny, hipMemcpyDefault,
+                                h->stream));
+    const size_t fq = dmrtk::FQ;
+    for (int64_t c = C - 1; c >= 0; --c) {
+        const int64_t len = std::min(S, n - c * S);
+        HIPCHK(hipMemcpyAsync(h->ring, h->ckpt + (size_t)c * sb, sb * sizeof(float),
+                              hipMemcpyDeviceToDevice, h->stream));
+        // recompute the segment, every state kept in the ring
+        for (int64_t j = 0; j < len; ++j) {
+            float* a = h->ring + (size_t)j * sb;
+            float* b = a + sb;
+            HIPCHK(hipMemcpyAsync(b + (fq + 6) * pl, a + (fq + 6) * pl, 2 * pl * sizeof(float),
+                                  hipMemcpyDeviceToDevice, h->stream));
+            dmrtk::StepBufs B;
+            B.fin = a;
+            B.fout = b;
+            B.gin = a + fq * pl;
+            B.gout = b + fq * pl;
+            B.flin = a + (fq + 5) * pl;
+            B.flout = b + (fq + 5) * pl;
+            B.ux = b + (fq + 6) * pl;
+            B.uy = b + (fq + 7) * pl;
+            B.eps = h->eps;
+            B.Ac = h->Ac;
+            B.Bc = h->Bc;
+            B.it_sum = B.it_max = nullptr;
+            HIPCHK(dmrtk::launch_step(G, h->P, B, h->flow, false, h->stream));
+        }
+        // reverse through the segment
+        for (int64_t j = len - 1; j >= 0; --j) {
+            const float* a = h->ring + (size_t)j * sb;
+            dmrtk::AdjBufs A;
+            A.f0 = a;
+            A.g0 = a + fq * pl;
+            A.fl0 = a + (fq + 5) * pl;
+            A.u0 = a + (fq + 6) * pl;
+            A.fl1 = a + sb + (fq + 5) * pl;
+            A.eps = h->eps;
+            A.Ac = h->Ac;
+            A.Bc = h->Bc;
+            A.ls = h->ls;
+            A.la = h->la;
+            A.ga = h->ga;
+            A.ls_out = h->ls;
+            HIPCHK(dmrtk::launch_adjoint_step(G, h->P, A, h->flow, h->stream));
+        }
+    }
+    // gradients: Ac = phi nu / (K (1-phi)^2), Bc = phi F / (sqrt(K) (1-phi))
+    std::vector<float> ga(3 * pl), he(pl), ha(pl), hb(pl);
+    HIPCHK(hipMemcpyAsync(ga.data(), h->ga, 3 * pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(he.data(), h->eps, pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(ha.data(), h->Ac, pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(hb.data(), h->Bc, pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const size_t ncell = (size_t)G.nx * G.ny;
+    std::vector<float> gk(ncell), gee(ncell);
+    for (int y = 0; y < G.ny; ++y)
+        for (int x = 0; x < G.nx; ++x) {
+            const size_t j = (size_t)y * G.pitch + x, i = (size_t)y * G.nx + x;
+            const double ep = he[j], Ac = ha[j], Bc = hb[j];
+            const double lE = ga[j], lA = ga[pl + j], lB = ga[2 * pl + j];
+            gk[i] = (float)(-Ac * lA - 0.5 * Bc * lB);
+            double ge = lE;
+            if (ep < 1.0) {
+                ge += lA * Ac * (1.0 / ep + 2.0 / (1.0 - ep));
+                ge += lB * Bc * (1.0 / ep + 1.0 / (1.0 - ep) - (h->feps_given ? 0.0 : 1.5 / ep));
+            }
+            gee[i] = (float)ge;
+        }
+    if (grad_logK) HIPCHK(hipMemcpyAsync(grad_logK, gk.data(), ncell * 4, hipMemcpyDefault, h->stream));
+    if (grad_eps) HIPCHK(hipMemcpyAsync(grad_eps, gee.data(), ncell * 4, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
 int64_t dmrt_time(const dmrt_t* h) { return h ? h->t : fail(DMRT_EINVAL, "null handle"); }
 
 int dmrt_sync(dmrt_t* h)
@@ -708,6 +896,7 @@ void dmrt_destroy(dmrt_t* h)
     if (h->base) (void)hipFree(h->base);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->it_sum) (void)hipFree(h->it_sum);
+    drop_recording(h);
     delete h;
 }
 

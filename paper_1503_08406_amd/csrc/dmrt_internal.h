@@ -109,6 +109,29 @@ int batch_blocks_per_cu(int rows);
 hipError_t launch_batch_count(const Cavity* cav, int ncav, const float* fl, const float* g,
                               long long* partials, int nblk, hipStream_t s);
 
+// Buffers of one reversed step k+1 -> k of the discrete adjoint.  A state
+// snapshot is ADJ_STATE planes: f (FQ), g (5), f_l, u_x, u_y.
+constexpr int ADJ_STATE = FQ + 5 + 1 + 2;
+constexpr int ADJ_LS = 18;  // state adjoint: d+ (9), rho - 1, g+ (5), f_l, u (2)
+constexpr int ADJ_LA = 32;  // local adjoints of one receiving node
+constexpr int ADJ_GA = 3;   // accumulated adjoints of porosity, Ac, Bc
+struct AdjBufs {
+    const float* f0;   // state k
+    const float* g0;
+    const float* fl0;
+    const float* u0;
+    const float* fl1;  // f_l^{k+1}
+    const float* eps;
+    const float* Ac;
+    const float* Bc;
+    const float* ls;   // adjoint of state k+1
+    float* la;         // local adjoints
+    float* ga;         // accumulators
+    float* ls_out;     // adjoint of state k (may alias ls)
+};
+hipError_t launch_adjoint_step(const Geom& G, const Phys& P, const AdjBufs& B, bool flow,
+                               hipStream_t s);
+
 // Load a pre-collision state (planar, row stride nx; any of f/g/fl may be
 // null) and store its post-collision populations into the current buffers.
 // eps/Ac/Bc may be null: the lattice then has the uniform values eps_u,

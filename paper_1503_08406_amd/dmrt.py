@@ -96,6 +96,9 @@ def _load():
         "dmrt_state_bytes": (C.c_int64, [P]),
         "dmrt_save": (C.c_int, [P, VP, C.c_size_t]),
         "dmrt_load": (C.c_int, [P, VP, C.c_size_t]),
+        "dmrt_set_porous": (C.c_int, [P, VP, VP, VP]),
+        "dmrt_record": (C.c_int, [P, C.c_int64]),
+        "dmrt_adjoint": (C.c_int, [P, VP, VP, VP, VP]),
         "dmrt_time": (C.c_int64, [P]),
         "dmrt_sync": (C.c_int, [P]),
         "dmrt_destroy": (None, [P]),
@@ -275,6 +278,34 @@ class Solver:
         buf = np.zeros(n, np.uint8)
         _check(_lib.dmrt_save(self._h, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
         return buf
+
+    def set_porous(self, eps, K=None, Feps=None):
+        """Replace the porous fields (float32 [ny, nx]; K / Feps None: the
+        defaults of dmrt_create)."""
+        shape = (self.ny, self.nx)
+        conv = lambda a: None if a is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(a, dtype=np.float32), shape))
+        e, k, f = conv(eps), conv(K), conv(Feps)
+        _check(_lib.dmrt_set_porous(self._h, _ptr(e), _ptr(k), _ptr(f)))
+
+    def reset(self):
+        """Back to the initial state (uniform T_init at rest)."""
+        _check(_lib.dmrt_set_state(self._h, None, None, None))
+
+    def record(self, n):
+        """Advance n steps keeping what dmrt_adjoint needs."""
+        _check(_lib.dmrt_record(self._h, int(n)))
+
+    def adjoint(self, dL_dT=None, dL_dfl=None):
+        """Gradients (dL/dlog K, dL/deps), float32 [ny, nx], of a loss of the
+        fields at the end of the recorded run with the given adjoints."""
+        shape = (self.ny, self.nx)
+        conv = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(shape))
+        gT, gf = conv(dL_dT), conv(dL_dfl)
+        gk = np.zeros(shape, np.float32)
+        ge = np.zeros(shape, np.float32)
+        _check(_lib.dmrt_adjoint(self._h, _ptr(gT), _ptr(gf), _ptr(gk), _ptr(ge)))
+        return gk, ge
 
     def load(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
