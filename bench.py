@@ -134,6 +134,58 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20):
             "liquid_cells_end": int(liq.sum())}
 
 
+def adjoint_timing(warm=200):
+    """The inverse-problem workload (512x512 cavity, Gaussian-random-field
+    log K seed 1, target run seed 2, 2000 steps): wall time of the plain
+    forward run, of the recorded forward run (checkpoints every ceil(sqrt n)
+    steps) and of the adjoint (segment recomputation plus the reversed
+    steps), all from the initial state.  The first adjoint call captures the
+    reversed pass as a HIP graph; the second, timed one replays it."""
+    import numpy as np
+    from paper_1503_08406_amd import workloads as W
+    from paper_1503_08406_amd.dmrt import Solver
+    case, target = W.adjoint_cavity(), W.adjoint_cavity(seed=2)
+    steps = case["steps"]
+    t = Solver(target, graph_steps=64)
+    t.step(steps)
+    Ft = t.fields()
+    t.close()
+    s = Solver(case, graph_steps=64)
+    s.step(warm)
+    s.sync()
+
+    def timed(fn):
+        s.sync()
+        t0 = time.perf_counter()
+        fn()
+        s.sync()
+        return (time.perf_counter() - t0) * 1e3
+
+    s.reset()
+    fwd = timed(lambda: s.step(steps))
+    s.reset()
+    rec = timed(lambda: s.record(steps))
+    F = s.fields()
+    dT, dfl = F["T"] - Ft["T"], F["fl"] - Ft["fl"]
+    loss = 0.5 * (float(np.sum(dT.astype(np.float64) ** 2)) + float(np.sum(dfl.astype(np.float64) ** 2)))
+    out = {}
+    adj_first = timed(lambda: out.setdefault("g0", s.adjoint(dT, dfl)))  # builds the graph
+    adj = timed(lambda: out.setdefault("g", s.adjoint(dT, dfl)))
+    gk, ge = out["g"]
+    assert np.array_equal(gk, out["g0"][0]) and np.array_equal(ge, out["g0"][1])
+    s.close()
+    return {"workload": "inverse problem: 512x512 cavity (Sec. 4.3 setting), Ra=1e5 Da=1e-3 Ste=1 "
+                        "eps=0.4, log K = log(Da H^2) + 0.5 GRF(corr 32, seed 1), target run "
+                        "seed 2, L = 1/2 sum((f_l - f_l*)^2 + (T - T*)^2) after 2000 steps",
+            "steps": steps, "forward_ms": round(fwd, 3), "record_ms": round(rec, 3),
+            "adjoint_ms": round(adj, 3), "adjoint_first_call_ms": round(adj_first, 3),
+            "adjoint_over_forward": round(adj / fwd, 3),
+            "record_and_adjoint_over_forward": round((rec + adj) / fwd, 3),
+            "loss": loss, "grad_logK_norm": float(np.linalg.norm(gk)),
+            "grad_eps_norm": float(np.linalg.norm(ge)),
+            "liquid_cells_end": int((F["fl"] > 0).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +202,7 @@ def main():
     ap.add_argument("--no-account", action="store_true", help="skip the phase accounting replay")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-cavity measurement")
     ap.add_argument("--batch-steps", type=int, default=0, help="batched steps (0: the workload's)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -245,6 +298,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched(mlups, steps=args.batch_steps or None)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_timing()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

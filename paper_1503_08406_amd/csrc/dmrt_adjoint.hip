@@ -11,15 +11,15 @@
 // and the liquid/solid classification of pull sources are held fixed; |v|
 // has the subgradient 0 at v = 0.  Requires uniform sigma and tau_T.
 //
-// One reversed step k+1 -> k is two launches:
-//   k_adj_local  (per receiving node x) recomputes the node's step from the
-//                stored state k (and f_l^{k+1}), back-propagates the adjoint
-//                of its outputs through the thermal collision, the flow
-//                closure and collision, the latent source and enthalpy
-//                update and the wall/interface extrapolations, and writes
-//                the adjoints of its pulled inputs and of its own state.
-//   k_adj_gather (per node y) adds to y's own terms the adjoints of the
-//                pulls made from y by its downstream neighbours y + e_i.
+// One reversed step k+1 -> k is one launch of k_adj_step per node x: it
+// first completes the adjoint of x's state at k+1 by gathering, from the
+// local adjoints the previous launch wrote, x's own terms and the adjoints
+// of the pulls its downstream neighbours x + e_i made from it; then it
+// recomputes x's step k from the stored state k (and f_l^{k+1}), back-
+// propagates through the thermal collision, the flow closure and
+// collision, the latent source and enthalpy update and the wall/interface
+// extrapolations, and writes the local adjoints of step k (the adjoints of
+// its pulled inputs and of its own state) for the next launch.
 #include "dmrt_device.h"
 
 namespace dmrtk {
@@ -163,9 +163,97 @@ __device__ __forceinline__ void flow_collide_adj(const float (&d)[9], float fl1,
     Ld[8] = L8 + Lsd - Lb68 - Lm8;
 }
 
-// Local adjoint of one receiving node (see the top of this file).
+// Adjoint of the state at step k+1 of node (x, y), gathered from the local
+// adjoints of step k+1 (la: written by the launch for step k+1): the node's
+// own terms plus the adjoints of the pulls its downstream neighbours y + e_i
+// made from it.  flA = f_l^{k+1}, flB = f_l^{k+2}: the flow part exists only
+// where the node was liquid at k+1, and a node's flow local adjoints only
+// where it was liquid at k+2.  L: d+ (0..8), rho - 1 (9), g+ (10..14),
+// f_l (15), u (16, 17).
 template <bool FLOW>
-__global__ __launch_bounds__(TX * TY) void k_adj_local(Geom G, Phys P, AdjBufs B)
+__device__ __forceinline__ void gather_state(const Geom& G, const float* __restrict__ la,
+                                             const float* __restrict__ flA,
+                                             const float* __restrict__ flB, int x, int y,
+                                             float (&L)[ADJ_LS])
+{
+    const size_t pl = (size_t)G.plane;
+    const size_t p = (size_t)G.pitch;
+    const size_t c = (size_t)y * p + (size_t)x;
+    const bool hx = x + 1 < G.nx || G.per_x, lx = x > 0 || G.per_x;
+    const bool hy = y + 1 < G.ny || G.per_y, ly = y > 0 || G.per_y;
+    const size_t xp = x + 1 < G.nx ? x + 1 : 0, xm = x > 0 ? x - 1 : G.nx - 1;
+    const size_t yp = y + 1 < G.ny ? y + 1 : 0, ym = y > 0 ? y - 1 : G.ny - 1;
+    bool ok[9];
+    size_t rc[9];  // receivers y + e_i
+    ok[0] = false;
+    rc[0] = c;
+    ok[1] = hx;
+    rc[1] = y * p + xp;
+    ok[2] = hy;
+    rc[2] = yp * p + x;
+    ok[3] = lx;
+    rc[3] = y * p + xm;
+    ok[4] = ly;
+    rc[4] = ym * p + x;
+    ok[5] = hx & hy;
+    rc[5] = yp * p + xp;
+    ok[6] = lx & hy;
+    rc[6] = yp * p + xm;
+    ok[7] = lx & ly;
+    rc[7] = ym * p + xm;
+    ok[8] = hx & ly;
+    rc[8] = ym * p + xp;
+    float t[10];  // own g terms (0..4), f_l (5), receivers' g pulls (6..9)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) t[i] = la[(15 + i) * pl + c];
+    t[5] = la[29 * pl + c];
+#pragma unroll
+    for (int i = 1; i < 5; ++i) t[5 + i] = la[i * pl + rc[i]];  // in-lattice even when absent
+    pin_loads(t);
+    L[10] = t[0];
+#pragma unroll
+    for (int i = 1; i < 5; ++i) L[10 + i] = t[i] + (ok[i] ? t[5 + i] : 0.0f);
+    L[15] = t[5];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) L[i] = 0.0f;
+    L[16] = L[17] = 0.0f;
+    if (FLOW && flA[c] > 0.0f) {
+        // every load in one batch (stale values of absent terms are loaded
+        // from in-lattice addresses and selected away)
+        float v[38];  // own d+ (0..8), receivers: f_l (9..16), pulls (17..24), restart (25..32), u (33, 34), own f_l (35)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = la[(20 + i) * pl + c];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            v[8 + i] = flB[rc[i]];
+            v[16 + i] = la[(5 + i) * pl + rc[i]];
+            v[24 + i] = la[14 * pl + rc[i]];
+        }
+        v[33] = la[30 * pl + c];
+        v[34] = la[31 * pl + c];
+        v[35] = flB[c];
+        v[36] = v[37] = 0.0f;
+        pin_loads(v);
+        const bool own1 = v[35] > 0.0f;
+        L[0] = own1 ? v[0] : 0.0f;
+        float Lr = 0.0f;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const bool rec = ok[i] && v[8 + i] > 0.0f;
+            L[i] = (own1 ? v[i] : 0.0f) + (rec ? v[16 + i] : 0.0f);
+            Lr += rec ? v[24 + i] : 0.0f;
+        }
+        L[9] = Lr;
+        L[16] = v[33];
+        L[17] = v[34];
+    }
+}
+
+// One reversed step k+1 -> k for one node: the adjoint of its state at
+// k+1 (the terminal adjoint when FIRST, else gathered from the local
+// adjoints of step k+1), then the local adjoint of its step k.
+template <bool FLOW, bool FIRST>
+__global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
 {
     int x, y;
     if (!tile_coords<TY>(G, x, y)) return;
@@ -239,24 +327,43 @@ __global__ __launch_bounds__(TX * TY) void k_adj_local(Geom G, Phys P, AdjBufs B
     const float eu[9] = {0.0f, uxk, uyk, -uxk, -uyk, uxk + uyk, uyk - uxk, -uxk - uyk, uxk - uyk};
     float ux = 0.0f, uy = 0.0f;
     if (liq1) {
-        if (liqk) {
+        // one batch: neighbour f_l, then the pulls and own values (liquid at
+        // k) or the neighbour densities (melted in this step)
+        float nf[9];
+        nf[0] = 0.0f;
 #pragma unroll
-            for (int i = 1; i < 9; ++i) liq |= (unsigned)(!wn[i] & (B.fl0[src[i]] > 0.0f)) << i;
-            d[0] = B.f0[c];
+        for (int i = 1; i < 9; ++i) nf[i] = B.fl0[src[i]];
+        if (liqk) {
+            float v[17];  // own f+_0..8 (0..8), pulls 1..8 (9..16)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[i] = B.f0[i * pl + c];
+#pragma unroll
+            for (int i = 1; i < 9; ++i) v[8 + i] = B.f0[i * pl + src[i]];
+            pin_loads(nf);
+            pin_loads(v);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) liq |= (unsigned)(!wn[i] & (nf[i] > 0.0f)) << i;
+            d[0] = v[0];
             iph = frcp(eps * flk);
             const float uu = 1.5f * (uxk * uxk + uyk * uyk) * iph;
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 const float e = eu[i];
-                d[i] = (liq & (1u << i)) ? B.f0[i * pl + src[i]]
-                                         : B.f0[i * pl + c] - w9(i) * (3.0f * e + 4.5f * e * e * iph - uu);
+                const float nee = v[i] - w9(i) * (3.0f * e + 4.5f * e * e * iph - uu);
+                d[i] = (liq & (1u << i)) ? v[8 + i] : nee;
             }
         } else {
+            float nr[9];
+            nr[0] = 0.0f;
+#pragma unroll
+            for (int k = 1; k < 9; ++k) nr[k] = B.f0[9 * pl + src[k]];
+            pin_loads(nf);
+            pin_loads(nr);
             float rsum = 0.0f;
 #pragma unroll
             for (int k = 1; k < 9; ++k)
-                if (!wn[k] && B.fl0[src[k]] > 0.0f) {
-                    rsum += B.f0[9 * pl + src[k]];
+                if (!wn[k] && nf[k] > 0.0f) {
+                    rsum += nr[k];
                     ++cnt;
                 }
             const float drho = cnt ? rsum * frcp((float)cnt) : 0.0f;
@@ -269,11 +376,20 @@ __global__ __launch_bounds__(TX * TY) void k_adj_local(Geom G, Phys P, AdjBufs B
         flow_collide(dd, fl1, eps, Ac, Bc, T1, P, ux, uy);
     }
 
+    // ---- adjoint of the outputs of this node's step (state k+1)
+    float Ls[ADJ_LS];
+    if (FIRST) {
+#pragma unroll
+        for (int i = 0; i < ADJ_LS; ++i) Ls[i] = B.ls[i * pl + c];
+    } else {
+        gather_state<FLOW>(G, B.la_prev, B.fl1, B.fl2, x, y, Ls);
+    }
+
     // ---- reverse: thermal collision (uniform zeta)
     float Lg[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) Lg[i] = B.ls[(10 + i) * pl + c];
-    float Lfl1 = B.ls[15 * pl + c];
+    for (int i = 0; i < 5; ++i) Lg[i] = Ls[10 + i];
+    float Lfl1 = Ls[15];
     float Leps = 0.0f, LAc = 0.0f, LBc = 0.0f, Lflk = 0.0f;
     const float za = P.zeta_a;
     const float ct = P.conv * T1 * isig1;
@@ -301,11 +417,11 @@ __global__ __launch_bounds__(TX * TY) void k_adj_local(Geom G, Phys P, AdjBufs B
         Lown_d[i] = 0.0f;
     }
     if (liq1) {
-        const float Lr = B.ls[9 * pl + c];  // rho - 1 stored as the sum of f+
+        const float Lr = Ls[9];  // rho - 1 stored as the sum of f+
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Ld[i] = B.ls[i * pl + c] + Lr;
-        Lux += B.ls[16 * pl + c];
-        Luy += B.ls[17 * pl + c];
+        for (int i = 0; i < 9; ++i) Ld[i] = Ls[i] + Lr;
+        Lux += Ls[16];
+        Luy += Ls[17];
         flow_collide_adj(d, fl1, eps, Ac, Bc, T1, P, Ld, Lux, Luy, Lfl1, Leps, LAc, LBc, LT1);
         if (liqk) {
             Lown_d[0] = Ld[0];
@@ -401,97 +517,41 @@ __global__ __launch_bounds__(TX * TY) void k_adj_local(Geom G, Phys P, AdjBufs B
         B.la[i * pl + c] = Lgp[i];
         B.la[(15 + i) * pl + c] = Lown_g[i];
     }
-    if (FLOW) {
+    // the flow planes only for a node liquid at k+1 (the gather reads them
+    // only there), u^k only for a node liquid at k; a node solid at k+1
+    // contributes nothing to Ac, Bc
+    if (liq1) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             B.la[(5 + i) * pl + c] = Ld[i];
             B.la[(20 + i) * pl + c] = Lown_d[i];
         }
         B.la[14 * pl + c] = Lrb;
+        B.ga[pl + c] += LAc;
+        B.ga[2 * pl + c] += LBc;
+    }
+    if (liqk) {  // u^k also enters the wall extrapolation of g
         B.la[30 * pl + c] = Luxk;
         B.la[31 * pl + c] = Luyk;
     }
     B.la[29 * pl + c] = Lflk;
-    B.ga[c] += Leps;
-    B.ga[pl + c] += LAc;
-    B.ga[2 * pl + c] += LBc;
-}
-
-// Gather: adjoint of the start-of-step state of node y.
-template <bool FLOW>
-__global__ __launch_bounds__(TX * TY) void k_adj_gather(Geom G, AdjBufs B)
-{
-    int x, y;
-    if (!tile_coords<TY>(G, x, y)) return;
-    const size_t pl = (size_t)G.plane;
-    const size_t p = (size_t)G.pitch;
-    const size_t c = (size_t)y * p + (size_t)x;
-    // receivers y + e_i (exists: inside the lattice or wrapped)
-    const bool hx = x + 1 < G.nx || G.per_x, lx = x > 0 || G.per_x;
-    const bool hy = y + 1 < G.ny || G.per_y, ly = y > 0 || G.per_y;
-    const size_t xp = x + 1 < G.nx ? x + 1 : 0, xm = x > 0 ? x - 1 : G.nx - 1;
-    const size_t yp = y + 1 < G.ny ? y + 1 : 0, ym = y > 0 ? y - 1 : G.ny - 1;
-    bool ok[9];
-    size_t rc[9];
-    ok[0] = false;
-    rc[0] = c;
-    ok[1] = hx;
-    rc[1] = y * p + xp;
-    ok[2] = hy;
-    rc[2] = yp * p + x;
-    ok[3] = lx;
-    rc[3] = y * p + xm;
-    ok[4] = ly;
-    rc[4] = ym * p + x;
-    ok[5] = hx & hy;
-    rc[5] = yp * p + xp;
-    ok[6] = lx & hy;
-    rc[6] = yp * p + xm;
-    ok[7] = lx & ly;
-    rc[7] = ym * p + xm;
-    ok[8] = hx & ly;
-    rc[8] = ym * p + xp;
-
-    B.ls_out[10 * pl + c] = B.la[15 * pl + c];
-#pragma unroll
-    for (int i = 1; i < 5; ++i) {
-        float v = B.la[(15 + i) * pl + c];
-        if (ok[i]) v += B.la[i * pl + rc[i]];
-        B.ls_out[(10 + i) * pl + c] = v;
-    }
-    B.ls_out[15 * pl + c] = B.la[29 * pl + c];
-    if (FLOW) {
-        B.ls_out[c] = B.la[20 * pl + c];
-        float Lr = 0.0f;
-        const bool liqk = B.fl0[c] > 0.0f;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            float v = B.la[(20 + i) * pl + c];
-            if (ok[i]) {
-                v += B.la[(5 + i) * pl + rc[i]];
-                if (liqk) Lr += B.la[14 * pl + rc[i]];
-            }
-            B.ls_out[i * pl + c] = v;
-        }
-        B.ls_out[9 * pl + c] = Lr;
-        B.ls_out[16 * pl + c] = B.la[30 * pl + c];
-        B.ls_out[17 * pl + c] = B.la[31 * pl + c];
-    }
+    if (Leps != 0.0f) B.ga[c] += Leps;
 }
 
 }  // namespace
 
 hipError_t launch_adjoint_step(const Geom& G, const Phys& P, const AdjBufs& B, bool flow,
-                               hipStream_t s)
+                               bool first, hipStream_t s)
 {
     const dim3 grd(tile_blocks(G, TY)), blk(TX, TY);
-    if (flow) {
-        hipLaunchKernelGGL(k_adj_local<true>, grd, blk, 0, s, G, P, B);
-        hipLaunchKernelGGL(k_adj_gather<true>, grd, blk, 0, s, G, B);
-    } else {
-        hipLaunchKernelGGL(k_adj_local<false>, grd, blk, 0, s, G, P, B);
-        hipLaunchKernelGGL(k_adj_gather<false>, grd, blk, 0, s, G, B);
-    }
+    if (flow && first)
+        hipLaunchKernelGGL((k_adj_step<true, true>), grd, blk, 0, s, G, P, B);
+    else if (flow)
+        hipLaunchKernelGGL((k_adj_step<true, false>), grd, blk, 0, s, G, P, B);
+    else if (first)
+        hipLaunchKernelGGL((k_adj_step<false, true>), grd, blk, 0, s, G, P, B);
+    else
+        hipLaunchKernelGGL((k_adj_step<false, false>), grd, blk, 0, s, G, P, B);
     return hipGetLastError();
 }
 

@@ -68,9 +68,12 @@ struct dmrt {
     bool feps_given = false;
     // recorded run for the adjoint: checkpoints every rec_S steps, the ring
     // of states of one segment, the adjoint buffers
-    int64_t rec_n = 0, rec_S = 0;
+    int64_t rec_n = 0, rec_S = 0, rec_cap = 0;  // rec_cap: n the buffers are sized for
     char* rec_base = nullptr;
     float *ckpt = nullptr, *ring = nullptr, *ls = nullptr, *la = nullptr, *ga = nullptr;
+    float* flnext = nullptr;  // f_l of the state after a segment's end
+    hipGraphExec_t adj_graph = nullptr;  // the reversed pass for rec_cap steps
+    bool adj_flow = false;
 };
 
 namespace {
@@ -241,6 +244,7 @@ dmrtk::StepBufs bufs(dmrt* h, bool counted)
     B.flout = h->fl[b];
     B.ux = h->ux;
     B.uy = h->uy;
+    B.uin = nullptr;
     B.eps = h->eps;
     B.Ac = h->Ac;
     B.Bc = h->Bc;
@@ -387,10 +391,76 @@ int porous_planes(dmrt* h, const float* eps, const float* K, const float* Feps,
 
 void drop_recording(dmrt* h)
 {
+    if (h->adj_graph) (void)hipGraphExecDestroy(h->adj_graph);
+    h->adj_graph = nullptr;
     if (h->rec_base) (void)hipFree(h->rec_base);
     h->rec_base = nullptr;
-    h->ckpt = h->ring = h->ls = h->la = h->ga = nullptr;
-    h->rec_n = h->rec_S = 0;
+    h->ckpt = h->ring = h->ls = h->la = h->ga = h->flnext = nullptr;
+    h->rec_n = h->rec_S = h->rec_cap = 0;
+}
+
+// Enqueue the reversed pass over a recorded run of n steps: per segment,
+// last segment first, recompute its states into the ring (the first read
+// from its checkpoint), then one adjoint launch per step, last step first;
+// the local adjoints alternate between two buffers.
+int enqueue_adjoint(dmrt* h)
+{
+    const Geom& G = h->G;
+    const size_t pl = (size_t)G.plane, sb = (size_t)dmrtk::ADJ_STATE * pl, fq = dmrtk::FQ;
+    const size_t la_n = (size_t)dmrtk::ADJ_LA * pl;
+    const int64_t n = h->rec_n, S = h->rec_S, C = (n + S - 1) / S;
+    int64_t r = 0;  // reversed steps enqueued so far
+    for (int64_t c = C - 1; c >= 0; --c) {
+        const int64_t len = std::min(S, n - c * S);
+        const float* ck = h->ckpt + (size_t)c * sb;
+        auto state = [&](int64_t j) { return j == 0 ? ck : h->ring + (size_t)j * sb; };
+        if (c < C - 1) {
+            // f_l of the state after this segment's end is the later
+            // segment's state 1, about to be overwritten in the ring
+            hipError_t e = dmrtk::launch_copy(h->flnext, h->ring + sb + (fq + 5) * pl, pl, h->stream);
+            if (e != hipSuccess) return fail(DMRT_EDEVICE, "copy launch: %s", hipGetErrorString(e));
+        }
+        for (int64_t j = 0; j < len; ++j) {
+            const float* a = state(j);
+            float* b = h->ring + (size_t)(j + 1) * sb;
+            dmrtk::StepBufs B;
+            B.fin = a;
+            B.fout = b;
+            B.gin = a + fq * pl;
+            B.gout = b + fq * pl;
+            B.flin = a + (fq + 5) * pl;
+            B.flout = b + (fq + 5) * pl;
+            B.ux = b + (fq + 6) * pl;
+            B.uy = b + (fq + 7) * pl;
+            B.uin = a + (fq + 6) * pl;
+            B.eps = h->eps;
+            B.Ac = h->Ac;
+            B.Bc = h->Bc;
+            B.it_sum = B.it_max = nullptr;
+            hipError_t e = dmrtk::launch_step(G, h->P, B, h->flow, false, h->stream);
+            if (e != hipSuccess) return fail(DMRT_EDEVICE, "recompute launch: %s", hipGetErrorString(e));
+        }
+        for (int64_t j = len - 1; j >= 0; --j, ++r) {
+            const float* a = state(j);
+            dmrtk::AdjBufs A;
+            A.f0 = a;
+            A.g0 = a + fq * pl;
+            A.fl0 = a + (fq + 5) * pl;
+            A.u0 = a + (fq + 6) * pl;
+            A.fl1 = h->ring + (size_t)(j + 1) * sb + (fq + 5) * pl;
+            A.fl2 = j + 2 <= len ? h->ring + (size_t)(j + 2) * sb + (fq + 5) * pl : h->flnext;
+            A.eps = h->eps;
+            A.Ac = h->Ac;
+            A.Bc = h->Bc;
+            A.ls = h->ls;
+            A.la_prev = h->la + (size_t)((r + 1) & 1) * la_n;
+            A.la = h->la + (size_t)(r & 1) * la_n;
+            A.ga = h->ga;
+            hipError_t e = dmrtk::launch_adjoint_step(G, h->P, A, h->flow, r == 0, h->stream);
+            if (e != hipSuccess) return fail(DMRT_EDEVICE, "adjoint launch: %s", hipGetErrorString(e));
+        }
+    }
+    return DMRT_OK;
 }
 
 int check_finite(dmrt* h)
@@ -734,7 +804,7 @@ int dmrt_set_porous(dmrt_t* h, const float* eps, const float* K, const float* Fe
     HIPCHK(hipMemcpyAsync(h->Bc, pb.data(), n, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->feps_given = Feps != nullptr;
-    drop_recording(h);
+    h->rec_n = 0;  // the recorded run no longer matches; buffers and graph are kept
     return DMRT_OK;
 }
 
@@ -745,25 +815,31 @@ int dmrt_record(dmrt_t* h, int64_t n)
     if (h->P.dsig != 0.0f || !h->P.zeta_uniform)
         return fail(DMRT_EINVAL, "the adjoint needs uniform sigma and tau_T (sigma_s == sigma_l, alpha_ratio == 1)");
     HIPCHK(hipSetDevice(h->dev));
-    drop_recording(h);
     int64_t S = 1;
     while (S * S < n) ++S;
     const int64_t C = (n + S - 1) / S;
     const size_t pl = (size_t)h->G.plane, sb = (size_t)dmrtk::ADJ_STATE * pl;
-    const size_t total = ((size_t)C * sb + (size_t)(S + 1) * sb +
-                          (size_t)(dmrtk::ADJ_LS + dmrtk::ADJ_LA + dmrtk::ADJ_GA) * pl) * sizeof(float);
-    hipError_t e = hipMalloc(&h->rec_base, total);
-    if (e != hipSuccess) {
-        h->rec_base = nullptr;
-        return fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE, "hipMalloc(%zu): %s", total,
-                    hipGetErrorString(e));
+    if (h->rec_cap != n) {
+        drop_recording(h);
+        const size_t total = ((size_t)C * sb + (size_t)(S + 1) * sb +
+                              (size_t)(dmrtk::ADJ_LS + 2 * dmrtk::ADJ_LA + dmrtk::ADJ_GA + 1) * pl) *
+                             sizeof(float);
+        hipError_t e = hipMalloc(&h->rec_base, total);
+        if (e != hipSuccess) {
+            h->rec_base = nullptr;
+            return fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE, "hipMalloc(%zu): %s",
+                        total, hipGetErrorString(e));
+        }
+        float* p = (float*)h->rec_base;
+        h->ckpt = p;
+        h->ring = p + (size_t)C * sb;
+        h->ls = h->ring + (size_t)(S + 1) * sb;
+        h->la = h->ls + (size_t)dmrtk::ADJ_LS * pl;
+        h->ga = h->la + (size_t)2 * dmrtk::ADJ_LA * pl;
+        h->flnext = h->ga + (size_t)dmrtk::ADJ_GA * pl;
+        h->rec_cap = n;
     }
-    float* p = (float*)h->rec_base;
-    h->ckpt = p;
-    h->ring = p + (size_t)C * sb;
-    h->ls = h->ring + (size_t)(S + 1) * sb;
-    h->la = h->ls + (size_t)dmrtk::ADJ_LS * pl;
-    h->ga = h->la + (size_t)dmrtk::ADJ_LA * pl;
+    h->rec_n = 0;
     const size_t fb = (size_t)dmrtk::FQ * pl * sizeof(float), pb = pl * sizeof(float);
     for (int64_t c = 0; c < C; ++c) {
         float* q = h->ckpt + (size_t)c * sb;
@@ -773,10 +849,7 @@ int dmrt_record(dmrt_t* h, int64_t n)
         HIPCHK(hipMemcpyAsync(q + (dmrtk::FQ + 5) * pl, h->fl[a], pb, hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(q + (dmrtk::FQ + 6) * pl, h->ux, 2 * pb, hipMemcpyDeviceToDevice, h->stream));
         int rc = dmrt_step(h, std::min(S, n - c * S));
-        if (rc) {
-            drop_recording(h);
-            return rc;
-        }
+        if (rc) return rc;
     }
     h->rec_n = n;
     h->rec_S = S;
@@ -790,11 +863,11 @@ int dmrt_adjoint(dmrt_t* h, const float* dL_dT, const float* dL_dfl, float* grad
     if (!h->rec_n) return fail(DMRT_EINVAL, "no recorded run (call dmrt_record first)");
     HIPCHK(hipSetDevice(h->dev));
     const Geom& G = h->G;
-    const size_t pl = (size_t)G.plane, sb = (size_t)dmrtk::ADJ_STATE * pl;
+    const size_t pl = (size_t)G.plane;
     const size_t pitch_b = (size_t)G.pitch * sizeof(float), row_b = (size_t)G.nx * sizeof(float);
-    const int64_t n = h->rec_n, S = h->rec_S, C = (n + S - 1) / S;
     // terminal adjoint: T = sum of g+, so dL/dg+_i = dL/dT for every i
-    HIPCHK(hipMemsetAsync(h->ls, 0, (size_t)(dmrtk::ADJ_LS + dmrtk::ADJ_LA + dmrtk::ADJ_GA) * pl * sizeof(float),
+    HIPCHK(hipMemsetAsync(h->ls, 0,
+                          (size_t)(dmrtk::ADJ_LS + 2 * dmrtk::ADJ_LA + dmrtk::ADJ_GA) * pl * sizeof(float),
                           h->stream));
     for (int i = 0; i < 5; ++i)
         if (dL_dT)
@@ -803,51 +876,31 @@ int dmrt_adjoint(dmrt_t* h, const float* dL_dT, const float* dL_dfl, float* grad
     if (dL_dfl)
         HIPCHK(hipMemcpy2DAsync(h->ls + 15 * pl, pitch_b, dL_dfl, row_b, row_b, G.ny, hipMemcpyDefault,
                                 h->stream));
-    const size_t fq = dmrtk::FQ;
-    for (int64_t c = C - 1; c >= 0; --c) {
-        const int64_t len = std::min(S, n - c * S);
-        HIPCHK(hipMemcpyAsync(h->ring, h->ckpt + (size_t)c * sb, sb * sizeof(float),
-                              hipMemcpyDeviceToDevice, h->stream));
-        // recompute the segment, every state kept in the ring
-        for (int64_t j = 0; j < len; ++j) {
-            float* a = h->ring + (size_t)j * sb;
-            float* b = a + sb;
-            HIPCHK(hipMemcpyAsync(b + (fq + 6) * pl, a + (fq + 6) * pl, 2 * pl * sizeof(float),
-                                  hipMemcpyDeviceToDevice, h->stream));
-            dmrtk::StepBufs B;
-            B.fin = a;
-            B.fout = b;
-            B.gin = a + fq * pl;
-            B.gout = b + fq * pl;
-            B.flin = a + (fq + 5) * pl;
-            B.flout = b + (fq + 5) * pl;
-            B.ux = b + (fq + 6) * pl;
-            B.uy = b + (fq + 7) * pl;
-            B.eps = h->eps;
-            B.Ac = h->Ac;
-            B.Bc = h->Bc;
-            B.it_sum = B.it_max = nullptr;
-            HIPCHK(dmrtk::launch_step(G, h->P, B, h->flow, false, h->stream));
-        }
-        // reverse through the segment
-        for (int64_t j = len - 1; j >= 0; --j) {
-            const float* a = h->ring + (size_t)j * sb;
-            dmrtk::AdjBufs A;
-            A.f0 = a;
-            A.g0 = a + fq * pl;
-            A.fl0 = a + (fq + 5) * pl;
-            A.u0 = a + (fq + 6) * pl;
-            A.fl1 = a + sb + (fq + 5) * pl;
-            A.eps = h->eps;
-            A.Ac = h->Ac;
-            A.Bc = h->Bc;
-            A.ls = h->ls;
-            A.la = h->la;
-            A.ga = h->ga;
-            A.ls_out = h->ls;
-            HIPCHK(dmrtk::launch_adjoint_step(G, h->P, A, h->flow, h->stream));
-        }
+    // the reversed pass: captured once per recording size and flow mode,
+    // replayed afterwards
+    if (h->adj_graph && h->adj_flow != h->flow) {
+        (void)hipGraphExecDestroy(h->adj_graph);
+        h->adj_graph = nullptr;
     }
+    if (!h->adj_graph) {
+        HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_adjoint(h);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(h->stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(DMRT_EDEVICE, "capture of the adjoint: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&h->adj_graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            h->adj_graph = nullptr;
+            return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        h->adj_flow = h->flow;
+    }
+    HIPCHK(hipGraphLaunch(h->adj_graph, h->stream));
     // gradients: Ac = phi nu / (K (1-phi)^2), Bc = phi F / (sqrt(K) (1-phi))
     std::vector<float> ga(3 * pl), he(pl), ha(pl), hb(pl);
     HIPCHK(hipMemcpyAsync(ga.data(), h->ga, 3 * pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));

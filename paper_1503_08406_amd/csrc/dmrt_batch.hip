@@ -53,6 +53,7 @@ __global__ __launch_bounds__(TX * TYB) void k_batch_step(BatchArgs a)
         B.flout = a.flout + C.fl_off;
         B.ux = a.u + C.u_off;
         B.uy = a.u + C.u_off + G.plane;
+        B.uin = nullptr;
         B.eps = B.Ac = B.Bc = nullptr;
         B.it_sum = B.it_max = nullptr;
         Arrays<BufIO> A(G, B);

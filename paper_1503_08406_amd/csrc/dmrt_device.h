@@ -70,6 +70,16 @@ __device__ __forceinline__ bool step_tile_origin(const Geom& G, int& x0, int& y0
     return true;
 }
 
+// Keeps a batch of loads together: the empty statement takes every value as
+// a register operand, so each load is issued on every path (none is sunk
+// into the branch that uses it) and the batch is waited for once, here.
+template <int N>
+__device__ __forceinline__ void pin_loads(float (&v)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]));
+}
+
 inline int tile_blocks(const Geom& G, int TYB)
 {
     const int tiles_x = (G.nx + TX - 1) / TX;

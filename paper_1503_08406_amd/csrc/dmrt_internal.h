@@ -63,8 +63,9 @@ struct StepBufs {
     float* __restrict__ gout;
     const float* __restrict__ flin;
     float* __restrict__ flout;
-    float* __restrict__ ux;
+    float* __restrict__ ux;        // u^{k+1} (ux plane, then the uy plane)
     float* __restrict__ uy;
+    const float* __restrict__ uin; // u^k when it lives elsewhere; null: read ux/uy
     const float* __restrict__ eps;
     const float* __restrict__ Ac;  // phi nu_l / (K (1-phi)^2): Darcy coefficient
     const float* __restrict__ Bc;  // phi F_eps / (sqrt(K) (1-phi)): Forchheimer
@@ -113,7 +114,7 @@ hipError_t launch_batch_count(const Cavity* cav, int ncav, const float* fl, cons
 // snapshot is ADJ_STATE planes: f (FQ), g (5), f_l, u_x, u_y.
 constexpr int ADJ_STATE = FQ + 5 + 1 + 2;
 constexpr int ADJ_LS = 18;  // state adjoint: d+ (9), rho - 1, g+ (5), f_l, u (2)
-constexpr int ADJ_LA = 32;  // local adjoints of one receiving node
+constexpr int ADJ_LA = 32;  // local adjoints of one receiving node (double-buffered)
 constexpr int ADJ_GA = 3;   // accumulated adjoints of porosity, Ac, Bc
 struct AdjBufs {
     const float* f0;   // state k
@@ -124,13 +125,14 @@ struct AdjBufs {
     const float* eps;
     const float* Ac;
     const float* Bc;
-    const float* ls;   // adjoint of state k+1
-    float* la;         // local adjoints
+    const float* fl2;  // f_l^{k+2} (unused by the first reversed step)
+    const float* ls;   // terminal adjoint (first reversed step only)
+    const float* la_prev;  // local adjoints of step k+1
+    float* la;         // local adjoints of step k
     float* ga;         // accumulators
-    float* ls_out;     // adjoint of state k (may alias ls)
 };
 hipError_t launch_adjoint_step(const Geom& G, const Phys& P, const AdjBufs& B, bool flow,
-                               hipStream_t s);
+                               bool first, hipStream_t s);
 
 // Load a pre-collision state (planar, row stride nx; any of f/g/fl may be
 // null) and store its post-collision populations into the current buffers.
@@ -142,6 +144,9 @@ hipError_t launch_load_state(const Geom& G, const Phys& P, const float* f_pre,
                              const float* eps, const float* Ac, const float* Bc,
                              bool flow, hipStream_t s, float eps_u = 0.0f, float Ac_u = 0.0f,
                              float Bc_u = 0.0f);
+
+// dst[0..n) = src[0..n) (a kernel, so that it can be captured in a graph).
+hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 
 // T, ux, uy, f_l into out[4][ny][nx].
 hipError_t launch_fields(const Geom& G, const float* gcur, const float* flcur,

@@ -3,8 +3,9 @@
 //
 // State layout in HBM (all float32, planar, x fastest, row pitch a multiple
 // of 64 elements so every row starts on a 256-byte boundary):
-//   f[2][9][ny][pitch]  post-collision D2Q9 populations stored as deviations
-//                       f_i - w_i rho0 (rho0 = 1), double-buffered
+//   f[2][10][ny][pitch] post-collision D2Q9 populations stored as deviations
+//                       f_i - w_i rho0 (rho0 = 1) and, in plane 9, rho - 1
+//                       of liquid nodes; double-buffered
 //   g[2][5][ny][pitch]  post-collision D2Q5 populations, double-buffered
 //   fl[2][ny][pitch]    liquid fraction, double-buffered
 //   ux, uy[ny][pitch]   velocity of the last step (read only by the same node
@@ -14,6 +15,8 @@
 // This file holds the auxiliary kernels (state loading, field extraction,
 // diagnostics); the time step itself is in dmrt_step.hip.
 #include "dmrt_device.h"
+
+#include <algorithm>
 
 namespace dmrtk {
 namespace {
@@ -64,6 +67,15 @@ __global__ __launch_bounds__(TX * TY) void k_load_state(Geom G, Phys P, const fl
 #pragma unroll
     for (int i = 0; i < 5; ++i) gcur[i * pl + c] = g[i];
     flcur[c] = fl;
+}
+
+// Plain copy of n floats (kept as a kernel so that it can sit in a graph).
+__global__ __launch_bounds__(256) void k_copy(float* __restrict__ dst, const float* __restrict__ src,
+                                              size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 __global__ __launch_bounds__(TX * TY) void k_fields(Geom G, const float* gcur, const float* flcur,
@@ -220,6 +232,13 @@ hipError_t launch_load_state(const Geom& G, const Phys& P, const float* f_pre, c
     else
         hipLaunchKernelGGL((k_load_state<false>), grd, blk, 0, s, G, P, f_pre, g_pre, fl_pre,
                            fcur, gcur, flcur, ux, uy, eps, Ac, Bc, eps_u, Ac_u, Bc_u);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, dst, src, n);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ namespace dmrtk {
 template <class IO>
 struct Arrays {
     typename IO::off_t pb;  // bytes per population plane
-    IO fin, fout, gin, gout, flin, flout, uv, stat;
+    IO fin, fout, gin, gout, flin, flout, uv, uvin, stat;
     // porosity and drag coefficients of a lattice with uniform porous fields
     // (used instead of the stat planes when the node functions are told so)
     float eps_u = 0.0f, Ac_u = 0.0f, Bc_u = 0.0f;
@@ -20,7 +20,8 @@ struct Arrays {
           fin(B.fin, FQ * (uint64_t)pb), fout(B.fout, FQ * (uint64_t)pb),
           gin(B.gin, 5 * (uint64_t)pb), gout(B.gout, 5 * (uint64_t)pb),
           flin(B.flin, pb), flout(B.flout, pb),
-          uv(B.ux, 2 * (uint64_t)pb),    // ux plane, then uy plane
+          uv(B.ux, 2 * (uint64_t)pb),    // ux plane, then uy plane (u^{k+1})
+          uvin(B.uin ? B.uin : B.ux, 2 * (uint64_t)pb),  // u^k
           stat(B.eps, 3 * (uint64_t)pb)  // eps, Ac, Bc planes
     {
     }
@@ -89,20 +90,10 @@ __device__ __forceinline__ void node_load(const Geom& G, const Arrays<IO>& A, in
         n.q[2] = A.gin.ld(o, 3 * pb);
         n.q[3] = A.gin.ld(o, 4 * pb);
         if (FLOW) {
-            n.uk[0] = A.uv.ld(o, 0);  // stale where the node is solid: masked later
-            n.uk[1] = A.uv.ld(o, pb);
+            n.uk[0] = A.uvin.ld(o, 0);  // stale where the node is solid: masked later
+            n.uk[1] = A.uvin.ld(o, pb);
         }
     }
-}
-
-// Keeps a batch of loads together: the empty statement takes every value as
-// a register operand, so each load is issued on every path (none is sunk
-// into the branch that uses it) and the batch is waited for once, here.
-template <int N>
-__device__ __forceinline__ void pin_loads(float (&v)[N])
-{
-#pragma unroll
-    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]));
 }
 
 // Thermal part of the step before the flow: wall sources of g (Eq. 36 with
@@ -228,8 +219,8 @@ __device__ __forceinline__ void node_flow(const Geom& G, const Phys& P, const Ar
         v[16] = fin.ld(o8, 8 * pb);
 #pragma unroll
         for (int i = 1; i < 9; ++i) v[16 + i] = fin.ld(o, (off_t)i * pb);
-        v[25] = uv.ld(o, 0);
-        v[26] = uv.ld(o, pb);
+        v[25] = A.uvin.ld(o, 0);
+        v[26] = A.uvin.ld(o, pb);
         pin_loads(v);
         const float n1 = v[0], n2 = v[1], n3 = v[2], n4 = v[3];
         const float n5 = v[4], n6 = v[5], n7 = v[6], n8 = v[7];

@@ -298,12 +298,24 @@ class Solver:
 
     def adjoint(self, dL_dT=None, dL_dfl=None):
         """Gradients (dL/dlog K, dL/deps), float32 [ny, nx], of a loss of the
-        fields at the end of the recorded run with the given adjoints."""
+        fields at the end of the recorded run with the given adjoints.  With
+        torch tensors the result is torch tensors on their device."""
         shape = (self.ny, self.nx)
-        conv = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(shape))
-        gT, gf = conv(dL_dT), conv(dL_dfl)
-        gk = np.zeros(shape, np.float32)
-        ge = np.zeros(shape, np.float32)
+        t = self.torch
+        if isinstance(dL_dT, t.Tensor) or isinstance(dL_dfl, t.Tensor):
+            ref = dL_dT if isinstance(dL_dT, t.Tensor) else dL_dfl
+            conv = lambda a: None if a is None else a.detach().to(t.float32).reshape(shape).contiguous()
+            gT, gf = conv(dL_dT), conv(dL_dfl)
+            gk = t.empty(shape, dtype=t.float32, device=ref.device)
+            ge = t.empty(shape, dtype=t.float32, device=ref.device)
+            if ref.is_cuda:
+                t.cuda.current_stream().synchronize()
+        else:
+            conv = lambda a: None if a is None else np.ascontiguousarray(
+                np.asarray(a, dtype=np.float32).reshape(shape))
+            gT, gf = conv(dL_dT), conv(dL_dfl)
+            gk = np.zeros(shape, np.float32)
+            ge = np.zeros(shape, np.float32)
         _check(_lib.dmrt_adjoint(self._h, _ptr(gT), _ptr(gf), _ptr(gk), _ptr(ge)))
         return gk, ge
 
@@ -430,3 +442,32 @@ class BatchSolver:
                 json.dump(db, fh, indent=1, sort_keys=True)
             os.replace(tmp, cache)
         return r.value, b.value, ms.value
+
+
+def melting_run(solver, logK, eps, steps):
+    """Differentiable run: (T, f_l) after `steps` steps from the initial state
+    of `solver` with per-cell log-permeability logK and porosity eps (torch
+    tensors [ny, nx]); gradients flow back to logK and eps through the
+    library's discrete adjoint (checkpointed recomputation)."""
+    import torch
+
+    class _MeltingRun(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, lk, ep):
+            K = torch.exp(lk.detach().double()).float().cpu().numpy()
+            solver.set_porous(ep.detach().float().cpu().numpy(), K)
+            solver.reset()
+            solver.record(steps)
+            F = solver.fields_device()
+            return F["T"].to(lk.device), F["fl"].to(lk.device)
+
+        @staticmethod
+        def backward(ctx, dT, dfl):
+            dev = dT.device if dT is not None else dfl.device
+            z = torch.zeros((solver.ny, solver.nx), dtype=torch.float32, device="cuda")
+            gT = z if dT is None else dT.to("cuda")
+            gF = z if dfl is None else dfl.to("cuda")
+            gk, ge = solver.adjoint(gT, gF)
+            return gk.to(dev), ge.to(dev)
+
+    return _MeltingRun.apply(logK, eps)

@@ -16,6 +16,8 @@ Workloads (the paper's three validation problems restated at new sizes):
                     log-normal permeability perturbation (sigma 0.1)
   cavity_batch      many Sec. 4.3 cavities of seeded uneven sizes and
                     parameters, uniform porous fields per cavity
+  adjoint_cavity    512x512 Sec. 4.3 cavity whose log-permeability is a
+                    seeded Gaussian random field (inverse-problem setting)
 """
 import math
 
@@ -114,6 +116,34 @@ def batch_member(cav, opts, steps=0):
     return make_case("batch_member", cav["nx"], cav["ny"], cav["bc_kind"], cav["T_wall"],
                      Ra=cav["Ra"], Da=cav["Da"], Pr=cav["Pr"], Ste=cav["Ste"], eps=cav["eps"],
                      steps=steps, H=cav.get("H", 0.0), **opts)
+
+
+def gaussian_field(nx, ny, corr, seed):
+    """Seeded Gaussian random field of unit standard deviation with the
+    covariance exp(-r^2 / (2 corr^2)): white noise convolved (periodically,
+    by FFT) with a Gaussian of width corr / sqrt(2), then normalised."""
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal((ny, nx))
+    kx = 2 * np.pi * np.fft.fftfreq(nx)
+    ky = 2 * np.pi * np.fft.fftfreq(ny)
+    k2 = kx[None, :] ** 2 + ky[:, None] ** 2
+    f = np.real(np.fft.ifft2(np.fft.fft2(xi) * np.exp(-k2 * corr * corr / 4.0)))
+    return (f - f.mean()) / f.std()
+
+
+def adjoint_cavity(n=512, steps=2000, seed=1, Ra=1e5, Da=1e-3, Ste=1.0, porosity=0.4,
+                   corr=32.0, sigma=0.5):
+    """Sec. 4.3 cavity (hot left wall, cold right wall, adiabatic top and
+    bottom, initially solid at theta = 0, theta_m = 9.78/25 +- 0.02) whose
+    permeability is K = Da H^2 exp(sigma xi), xi a Gaussian random field of
+    correlation length corr (H = n); porosity uniform.  The parameters of
+    the inverse problem use seed 1, its target run seed 2."""
+    xi = gaussian_field(n, n, corr, seed)
+    K = Da * float(n) ** 2 * np.exp(sigma * xi)
+    return make_case("adjoint_cavity", n, n, [WALL_T, WALL_T, WALL_ADIABATIC, WALL_ADIABATIC],
+                     [1.0, 0.0, 0.0, 0.0], Ra=Ra, Da=Da, Pr=1.0, Ste=Ste, eps=porosity, K=K,
+                     steps=steps, T_init=0.0, T_s=THETA_M_CAVITY - 0.02,
+                     T_l=THETA_M_CAVITY + 0.02, convective=1)
 
 
 def periodic_box(nx, ny, T, fl_phase="liquid", Ra=1e5, Da=1e-2, Pr=1.0, Ste=1.0,

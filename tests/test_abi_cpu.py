@@ -163,3 +163,11 @@ def test_batch_calls_reject_null_handles():
     assert lib.dmrt_batch_tune(None, 1, None, None, None) == dmrt.DMRT_EINVAL
     assert lib.dmrt_batch_set_launch(None, 4, 0) == dmrt.DMRT_EINVAL
     lib.dmrt_batch_destroy(None)
+
+
+def test_adjoint_calls_reject_null_handles():
+    from paper_1503_08406_amd import dmrt
+    lib = dmrt.lib()
+    assert lib.dmrt_record(None, 10) == dmrt.DMRT_EINVAL
+    assert lib.dmrt_adjoint(None, None, None, None, None) == dmrt.DMRT_EINVAL
+    assert lib.dmrt_set_porous(None, None, None, None) == dmrt.DMRT_EINVAL

@@ -104,3 +104,92 @@ def test_adjoint_matches_oracle_finite_differences(kind):
     F2 = s.fields()
     for k in F:
         assert np.array_equal(F[k], F2[k])
+
+
+def _loss(T, fl, Ts, fs):
+    return 0.5 * (((T - Ts) ** 2).sum() + ((fl - fs) ** 2).sum())
+
+
+def test_torch_function_and_directional_derivative():
+    """The torch.autograd.Function gives the library's adjoint gradients, and
+    a central difference of the GPU forward along a random direction matches
+    the directional derivative."""
+    import torch
+    from paper_1503_08406_amd.dmrt import Solver, melting_run
+    case, steps, _, _ = _case("liquid")
+    s = Solver(case, fl_tol=1e-7)
+    rng = np.random.default_rng(5)
+    lk0 = torch.tensor(np.log(case["K"].astype(np.float64)), dtype=torch.float32, device="cuda")
+    ep0 = torch.tensor(case["eps"], dtype=torch.float32, device="cuda")
+    # target: the run with a perturbed permeability field
+    with torch.no_grad():
+        Ts, fs = melting_run(s, lk0 + 0.3 * torch.tensor(rng.standard_normal(lk0.shape),
+                                                         dtype=torch.float32, device="cuda"), ep0, steps)
+        Ts, fs = Ts.clone(), fs.clone()
+    lk = lk0.clone().requires_grad_(True)
+    ep = ep0.clone().requires_grad_(True)
+    T, fl = melting_run(s, lk, ep, steps)
+    L = _loss(T.double(), fl.double(), Ts.double(), fs.double())
+    L.backward()
+    gk, ge = s.adjoint((T - Ts).detach(), (fl - fs).detach())
+    assert torch.equal(lk.grad, gk) and torch.equal(ep.grad, ge)
+    vk = torch.tensor(rng.standard_normal(lk0.shape), dtype=torch.float32, device="cuda")
+    ve = 0.02 * torch.tensor(rng.standard_normal(lk0.shape), dtype=torch.float32, device="cuda")
+    dd = float((lk.grad * vk).sum() + (ep.grad * ve).sum())
+    h = 1e-2
+    with torch.no_grad():
+        Lp = _loss(*[a.double() for a in melting_run(s, lk0 + h * vk, ep0 + h * ve, steps)],
+                   Ts.double(), fs.double())
+        Lm = _loss(*[a.double() for a in melting_run(s, lk0 - h * vk, ep0 - h * ve, steps)],
+                   Ts.double(), fs.double())
+    fd = float(Lp - Lm) / (2 * h)
+    _say("directional derivative: adjoint %.6e, central difference %.6e" % (dd, fd))
+    assert abs(dd - fd) <= 2e-2 * abs(fd)
+
+
+def test_adjoint_full_size_inverse_problem():
+    """The inverse-problem workload (512x512 cavity, Gaussian-random-field
+    log K, seed 1; target run seed 2; 2000 steps) in the configuration the
+    benchmark times: finite gradients, zero log K gradient away from the
+    melted region (K enters only through the flow of liquid nodes), and a
+    central difference of the GPU forward along the gradient direction that
+    matches the gradient norm."""
+    import torch
+    from paper_1503_08406_amd.dmrt import Solver, melting_run
+    case = W.adjoint_cavity()
+    target = W.adjoint_cavity(seed=2)
+    steps = case["steps"]
+    s = Solver(case, graph_steps=64)
+    lk0 = torch.tensor(np.log(case["K"].astype(np.float64)), dtype=torch.float32, device="cuda")
+    ep0 = torch.tensor(case["eps"], dtype=torch.float32, device="cuda")
+    with torch.no_grad():
+        Ts, fs = melting_run(s, torch.tensor(np.log(target["K"].astype(np.float64)),
+                                             dtype=torch.float32, device="cuda"), ep0, steps)
+        Ts, fs = Ts.clone(), fs.clone()
+    lk = lk0.clone().requires_grad_(True)
+    T, fl = melting_run(s, lk, ep0, steps)
+    L = _loss(T.double(), fl.double(), Ts.double(), fs.double())
+    L.backward()
+    g = lk.grad
+    assert torch.isfinite(g).all()
+    liquid = (fl > 0).cpu().numpy()
+    near = liquid.copy()
+    for _ in range(3):  # within 3 nodes of the final liquid region
+        near = near | np.roll(near, 1, 0) | np.roll(near, -1, 0) | np.roll(near, 1, 1) | np.roll(near, -1, 1)
+    gn = g.cpu().numpy()
+    _say("inverse problem: L %.6e, liquid %d, |g| %.3e" % (float(L), int(liquid.sum()),
+                                                           float(g.norm())))
+    assert liquid.sum() > 0 and np.all(gn[~near] == 0.0) and np.abs(gn[liquid]).max() > 0
+    # v = g / |g| is spread over the melted strip, so a step h changes no
+    # node's log K by more than h max|v| (~0.05 at h = 1); L is ~1e-7, so a
+    # small h would only measure the FP32 rounding of the forward run
+    v = g / g.norm()
+    fds = []
+    for h in (0.5, 1.0):
+        with torch.no_grad():
+            Lp = _loss(*[a.double() for a in melting_run(s, lk0 + h * v, ep0, steps)], Ts.double(), fs.double())
+            Lm = _loss(*[a.double() for a in melting_run(s, lk0 - h * v, ep0, steps)], Ts.double(), fs.double())
+        fds.append(float(Lp - Lm) / (2 * h))
+    _say("inverse problem: |g| %.6e, max|v| %.3f, central differences along g %s"
+         % (float(g.norm()), float(v.abs().max()), fds))
+    assert abs(fds[-1] - float(g.norm())) <= 5e-2 * float(g.norm())
