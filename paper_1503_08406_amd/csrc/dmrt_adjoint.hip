@@ -538,7 +538,59 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
     if (Leps != 0.0f) B.ga[c] += Leps;
 }
 
+// Terminal adjoint of a loss of the final fields: T = sum of g+, so every
+// g+ plane gets dL/dT; f_l gets dL/df_l (packed inputs, nx*ny; null = 0).
+__global__ __launch_bounds__(TX * TY) void k_adj_terminal(Geom G, const float* dT, const float* dfl,
+                                                          float* ls)
+{
+    int x, y;
+    if (!tile_coords<TY>(G, x, y)) return;
+    const size_t pl = (size_t)G.plane, c = (size_t)y * G.pitch + x, i = (size_t)y * G.nx + x;
+    const float t = dT ? dT[i] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ls[(10 + k) * pl + c] = t;
+    ls[15 * pl + c] = dfl ? dfl[i] : 0.0f;
+}
+
+// Gradients per cell from the accumulated adjoints of porosity (direct
+// terms), Ac and Bc: Ac = phi nu / (K (1-phi)^2) and Bc = phi F / (sqrt(K)
+// (1-phi)) give dAc/dlog K = -Ac, dBc/dlog K = -Bc/2, dAc/dphi = Ac (1/phi +
+// 2/(1-phi)), dBc/dphi = Bc (1/phi + 1/(1-phi) + dlog F/dphi) with
+// dlog F/dphi = -3/(2 phi) for the Ergun relation (0 when F was given).
+__global__ __launch_bounds__(TX * TY) void k_adj_grads(Geom G, const float* ga, const float* eps,
+                                                       const float* Ac, const float* Bc, int ergun,
+                                                       float* gk, float* ge)
+{
+    int x, y;
+    if (!tile_coords<TY>(G, x, y)) return;
+    const size_t pl = (size_t)G.plane, c = (size_t)y * G.pitch + x, i = (size_t)y * G.nx + x;
+    const double ep = eps[c], a = Ac[c], b = Bc[c];
+    const double lE = ga[c], lA = ga[pl + c], lB = ga[2 * pl + c];
+    gk[i] = (float)(-a * lA - 0.5 * b * lB);
+    double g = lE;
+    if (ep < 1.0) {
+        g += lA * a * (1.0 / ep + 2.0 / (1.0 - ep));
+        g += lB * b * (1.0 / ep + 1.0 / (1.0 - ep) - (ergun ? 1.5 / ep : 0.0));
+    }
+    ge[i] = (float)g;
+}
+
 }  // namespace
+
+hipError_t launch_adjoint_terminal(const Geom& G, const float* dT, const float* dfl, float* ls,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_terminal, dim3(tile_blocks(G, TY)), dim3(TX, TY), 0, s, G, dT, dfl, ls);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_grads(const Geom& G, const float* ga, const float* eps, const float* Ac,
+                                const float* Bc, bool ergun, float* gk, float* ge, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_grads, dim3(tile_blocks(G, TY)), dim3(TX, TY), 0, s, G, ga, eps, Ac,
+                       Bc, (int)ergun, gk, ge);
+    return hipGetLastError();
+}
 
 hipError_t launch_adjoint_step(const Geom& G, const Phys& P, const AdjBufs& B, bool flow,
                                bool first, hipStream_t s)

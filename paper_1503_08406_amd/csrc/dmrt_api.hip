@@ -72,6 +72,7 @@ struct dmrt {
     char* rec_base = nullptr;
     float *ckpt = nullptr, *ring = nullptr, *ls = nullptr, *la = nullptr, *ga = nullptr;
     float* flnext = nullptr;  // f_l of the state after a segment's end
+    float* stage = nullptr;   // two packed nx*ny planes: terminal adjoints in, gradients out
     hipGraphExec_t adj_graph = nullptr;  // the reversed pass for rec_cap steps
     bool adj_flow = false;
 };
@@ -395,7 +396,7 @@ void drop_recording(dmrt* h)
     h->adj_graph = nullptr;
     if (h->rec_base) (void)hipFree(h->rec_base);
     h->rec_base = nullptr;
-    h->ckpt = h->ring = h->ls = h->la = h->ga = h->flnext = nullptr;
+    h->ckpt = h->ring = h->ls = h->la = h->ga = h->flnext = h->stage = nullptr;
     h->rec_n = h->rec_S = h->rec_cap = 0;
 }
 
@@ -822,7 +823,8 @@ int dmrt_record(dmrt_t* h, int64_t n)
     if (h->rec_cap != n) {
         drop_recording(h);
         const size_t total = ((size_t)C * sb + (size_t)(S + 1) * sb +
-                              (size_t)(dmrtk::ADJ_LS + 2 * dmrtk::ADJ_LA + dmrtk::ADJ_GA + 1) * pl) *
+                              (size_t)(dmrtk::ADJ_LS + 2 * dmrtk::ADJ_LA + dmrtk::ADJ_GA + 1) * pl +
+                              2 * (size_t)h->G.nx * h->G.ny) *
                              sizeof(float);
         hipError_t e = hipMalloc(&h->rec_base, total);
         if (e != hipSuccess) {
@@ -837,6 +839,7 @@ int dmrt_record(dmrt_t* h, int64_t n)
         h->la = h->ls + (size_t)dmrtk::ADJ_LS * pl;
         h->ga = h->la + (size_t)2 * dmrtk::ADJ_LA * pl;
         h->flnext = h->ga + (size_t)dmrtk::ADJ_GA * pl;
+        h->stage = h->flnext + pl;
         h->rec_cap = n;
     }
     h->rec_n = 0;
@@ -864,18 +867,18 @@ int dmrt_adjoint(dmrt_t* h, const float* dL_dT, const float* dL_dfl, float* grad
     HIPCHK(hipSetDevice(h->dev));
     const Geom& G = h->G;
     const size_t pl = (size_t)G.plane;
-    const size_t pitch_b = (size_t)G.pitch * sizeof(float), row_b = (size_t)G.nx * sizeof(float);
-    // terminal adjoint: T = sum of g+, so dL/dg+_i = dL/dT for every i
+    // terminal adjoint (staged through two packed planes: one contiguous copy
+    // each, from host or device memory)
     HIPCHK(hipMemsetAsync(h->ls, 0,
                           (size_t)(dmrtk::ADJ_LS + 2 * dmrtk::ADJ_LA + dmrtk::ADJ_GA) * pl * sizeof(float),
                           h->stream));
-    for (int i = 0; i < 5; ++i)
-        if (dL_dT)
-            HIPCHK(hipMemcpy2DAsync(h->ls + (size_t)(10 + i) * pl, pitch_b, dL_dT, row_b, row_b, G.ny,
-                                    hipMemcpyDefault, h->stream));
-    if (dL_dfl)
-        HIPCHK(hipMemcpy2DAsync(h->ls + 15 * pl, pitch_b, dL_dfl, row_b, row_b, G.ny, hipMemcpyDefault,
-                                h->stream));
+    const size_t ncell = (size_t)G.nx * G.ny;
+    float* sT = h->stage;
+    float* sF = h->stage + ncell;
+    if (dL_dT) HIPCHK(hipMemcpyAsync(sT, dL_dT, ncell * sizeof(float), hipMemcpyDefault, h->stream));
+    if (dL_dfl) HIPCHK(hipMemcpyAsync(sF, dL_dfl, ncell * sizeof(float), hipMemcpyDefault, h->stream));
+    HIPCHK(dmrtk::launch_adjoint_terminal(G, dL_dT ? sT : nullptr, dL_dfl ? sF : nullptr, h->ls,
+                                          h->stream));
     // the reversed pass: captured once per recording size and flow mode,
     // replayed afterwards
     if (h->adj_graph && h->adj_flow != h->flow) {
@@ -901,30 +904,11 @@ int dmrt_adjoint(dmrt_t* h, const float* dL_dT, const float* dL_dfl, float* grad
         h->adj_flow = h->flow;
     }
     HIPCHK(hipGraphLaunch(h->adj_graph, h->stream));
-    // gradients: Ac = phi nu / (K (1-phi)^2), Bc = phi F / (sqrt(K) (1-phi))
-    std::vector<float> ga(3 * pl), he(pl), ha(pl), hb(pl);
-    HIPCHK(hipMemcpyAsync(ga.data(), h->ga, 3 * pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(he.data(), h->eps, pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(ha.data(), h->Ac, pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(hb.data(), h->Bc, pl * sizeof(float), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    const size_t ncell = (size_t)G.nx * G.ny;
-    std::vector<float> gk(ncell), gee(ncell);
-    for (int y = 0; y < G.ny; ++y)
-        for (int x = 0; x < G.nx; ++x) {
-            const size_t j = (size_t)y * G.pitch + x, i = (size_t)y * G.nx + x;
-            const double ep = he[j], Ac = ha[j], Bc = hb[j];
-            const double lE = ga[j], lA = ga[pl + j], lB = ga[2 * pl + j];
-            gk[i] = (float)(-Ac * lA - 0.5 * Bc * lB);
-            double ge = lE;
-            if (ep < 1.0) {
-                ge += lA * Ac * (1.0 / ep + 2.0 / (1.0 - ep));
-                ge += lB * Bc * (1.0 / ep + 1.0 / (1.0 - ep) - (h->feps_given ? 0.0 : 1.5 / ep));
-            }
-            gee[i] = (float)ge;
-        }
-    if (grad_logK) HIPCHK(hipMemcpyAsync(grad_logK, gk.data(), ncell * 4, hipMemcpyDefault, h->stream));
-    if (grad_eps) HIPCHK(hipMemcpyAsync(grad_eps, gee.data(), ncell * 4, hipMemcpyDefault, h->stream));
+    // gradients, assembled on the device into the two staging planes
+    HIPCHK(dmrtk::launch_adjoint_grads(G, h->ga, h->eps, h->Ac, h->Bc, !h->feps_given, sT, sF,
+                                       h->stream));
+    if (grad_logK) HIPCHK(hipMemcpyAsync(grad_logK, sT, ncell * 4, hipMemcpyDefault, h->stream));
+    if (grad_eps) HIPCHK(hipMemcpyAsync(grad_eps, sF, ncell * 4, hipMemcpyDefault, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return DMRT_OK;
 }

@@ -133,6 +133,12 @@ struct AdjBufs {
 };
 hipError_t launch_adjoint_step(const Geom& G, const Phys& P, const AdjBufs& B, bool flow,
                                bool first, hipStream_t s);
+// Terminal state adjoint from packed dL/dT, dL/df_l (either may be null).
+hipError_t launch_adjoint_terminal(const Geom& G, const float* dT, const float* dfl, float* ls,
+                                   hipStream_t s);
+// Packed gradients with respect to log K and porosity from the accumulators.
+hipError_t launch_adjoint_grads(const Geom& G, const float* ga, const float* eps, const float* Ac,
+                                const float* Bc, bool ergun, float* gk, float* ge, hipStream_t s);
 
 // Load a pre-collision state (planar, row stride nx; any of f/g/fl may be
 // null) and store its post-collision populations into the current buffers.
