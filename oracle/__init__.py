@@ -5,8 +5,8 @@ baseline leg of the benchmark may import this package.  The product library
 never does.
 """
 from .oracle import (OracleSim, build, make_params, lattice, feq, meq, force_moments, geq,
-                     neq, collide_f, closure, enthalpy, derive, default_params)
+                     neq, collide_f, closure, enthalpy, ke, derive, default_params)
 
 __all__ = ["OracleSim", "build", "make_params", "lattice", "feq", "meq", "force_moments",
-           "geq", "neq", "collide_f", "closure", "enthalpy", "derive",
+           "geq", "neq", "collide_f", "closure", "enthalpy", "ke", "derive",
            "default_params"]

@@ -204,11 +204,51 @@ void orc_default_params(orc_params *p)
     p->fl_maxit = 200;
     p->convective = 1;
     p->nthreads = 0;
+    p->sigma_mode = 0;
+    p->cps_ratio = 1;
+    p->cm_ratio = 1;
+    p->ke_mode = 0;
+    p->ks_ratio = 1;
+    p->km_ratio = 1;
+    p->latent_mode = 0;
 }
 
-static double sigma_of(const orc_params *p, double fl)
+/* c_ps / c_pl: the capacities differ only in the Eq. (7) variant. */
+static double cps_of(const orc_params *p)
 {
+    return p->sigma_mode == 1 ? p->cps_ratio : 1.0;
+}
+
+/* Heat-capacity ratio of a cell.  Mode 0: linear between the given solid
+ * and liquid values.  Mode 1: Eq. (7) with rho_s = rho_l, i.e.
+ * sigma = phi (f_l + (1 - f_l) c_ps / c_pl) + (1 - phi) (rho c_p)_m / (rho c_pl). */
+static double sigma_of(const orc_params *p, double eps, double fl)
+{
+    if (p->sigma_mode == 1)
+        return eps * (fl + (1.0 - fl) * p->cps_ratio) + (1.0 - eps) * p->cm_ratio;
     return p->sigma_s + fl * (p->sigma_l - p->sigma_s);
+}
+
+/* Eq. (8) in units of k_l: with z = k_e^(1/3) it is the depressed cubic
+ * z^3 + P z + Q = 0, P = phi (k_m - k_p) / k_p^(1/3), Q = -k_m, solved by
+ * Cardano's formula (one real root when (Q/2)^2 + (P/3)^3 >= 0, otherwise
+ * the largest of the three real roots, trigonometric form). */
+double orc_ke(double phi, double fl, double ks_ratio, double km_ratio)
+{
+    double kp = fl + (1.0 - fl) * ks_ratio;
+    double P = phi * (km_ratio - kp) / cbrt(kp);
+    double Q = -km_ratio;
+    double D = 0.25 * Q * Q + P * P * P / 27.0;
+    double z;
+    if (D >= 0) {
+        double sD = sqrt(D);
+        z = cbrt(-0.5 * Q + sD) + cbrt(-0.5 * Q - sD);
+    } else {
+        double r = sqrt(-P / 3.0);
+        double th = acos(1.5 * Q / (P * r)) / 3.0;
+        z = 2.0 * r * cos(th);
+    }
+    return z * z * z;
 }
 
 int orc_derive(const orc_params *p, orc_derived *d)
@@ -243,11 +283,15 @@ int orc_derive(const orc_params *p, orc_derived *d)
     return 0;
 }
 
-/* alpha_e(f_l) = alpha_l f_l + alpha_s (1 - f_l), scaled by lambda (Sec. 4.1, 4.3). */
-static double tauT_of(const orc_params *p, const orc_derived *d, double fl)
+/* tau_T = 1/2 + alpha_e / (sigma c_sT^2 dt).  Mode 0: alpha_e = lambda
+ * (alpha_l f_l + alpha_s (1 - f_l)) (Sec. 4.1, 4.3); mode 1: alpha_e =
+ * k_e / (rho c_pl) = alpha_l k_e / k_l with k_e from Eq. (8). */
+static double tauT_of(const orc_params *p, const orc_derived *d, double eps, double fl)
 {
-    double alpha_e = p->lambda_ * (d->alpha_l * fl + d->alpha_s * (1.0 - fl));
-    return 0.5 + alpha_e / (sigma_of(p, fl) * d->csT2 * DT);
+    double alpha_e = p->ke_mode == 1
+        ? d->alpha_l * orc_ke(eps, fl, p->ks_ratio, p->km_ratio)
+        : p->lambda_ * (d->alpha_l * fl + d->alpha_s * (1.0 - fl));
+    return 0.5 + alpha_e / (sigma_of(p, eps, fl) * d->csT2 * DT);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -378,12 +422,13 @@ void orc_closure(double jx, double jy, double phi, double nu_l, double Ke, doubl
     F[1] = -phi * nu_l / Ke * u[1] - phi * Ce / sqrt(Ke) * umag * u[1] + phi * Gy;
 }
 
-/* Eq. (41): temperature from total enthalpy (c_ps = c_pl = 1). */
-static double T_of_En(double En, double T_s, double T_l, double Ste)
+/* Eq. (41): temperature from total enthalpy, in units with c_pl = 1 and
+ * L_a / c_pl = 1/St; cps = c_ps / c_pl. */
+static double T_of_En(double En, double T_s, double T_l, double Ste, double cps)
 {
-    double En_s = T_s;             /* c_ps T_s */
-    double En_l = T_l + 1.0 / Ste; /* c_pl T_l + L_a, L_a / c_pl = 1/St */
-    if (En <= En_s) return En;
+    double En_s = cps * T_s;       /* c_ps T_s */
+    double En_l = T_l + 1.0 / Ste; /* c_pl T_l + L_a */
+    if (En <= En_s) return En / cps;
     if (En >= En_l) return T_l + (En - En_l);
     return T_s + (En - En_s) / (En_l - En_s) * (T_l - T_s);
 }
@@ -396,11 +441,18 @@ static double fl_of_T(double T, double T_s, double T_l)
     return (T - T_s) / (T_l - T_s);
 }
 
+/* Eq. (40) with c_p of the mixture, f_l c_pl + (1 - f_l) c_ps. */
+static double En_of(double T, double f, double Ste, double cps)
+{
+    return (f + (1.0 - f) * cps) * T + f / Ste;
+}
+
 /* Iterated enthalpy method (Sec. 3.2, end): the latent source of Eq. (38)
  * needs f_l(t+dt); iterate T <- T* + S0(f), En (Eq. 40), T(En) (Eq. 41),
- * f_l(T) (Eq. 42) until f_l stops changing. */
+ * f_l(T) (Eq. 42) until f_l stops changing.  sigma = sigma_s + f (sigma_l -
+ * sigma_s); cps = c_ps / c_pl (1 unless the heat capacities differ). */
 int orc_enthalpy(double Tstar, double fl_old, double eps, double Ste, double sigma_s,
-                 double sigma_l, double T_s, double T_l, double tol, int maxit,
+                 double sigma_l, double cps, double T_s, double T_l, double tol, int maxit,
                  double *fl_new, double *T_new)
 {
     double f = fl_old;
@@ -410,8 +462,8 @@ int orc_enthalpy(double Tstar, double fl_old, double eps, double Ste, double sig
         double sig = sigma_s + f * (sigma_l - sigma_s);
         double S0 = -(eps / (sig * Ste)) * (f - fl_old) / DT; /* Eq. (38) */
         double T = Tstar + DT * S0;                            /* zeroth moment of Eq. (35) */
-        double En = T + f / Ste;                               /* Eq. (40) */
-        double fn = fl_of_T(T_of_En(En, T_s, T_l, Ste), T_s, T_l);
+        double En = En_of(T, f, Ste, cps);                     /* Eq. (40) */
+        double fn = fl_of_T(T_of_En(En, T_s, T_l, Ste, cps), T_s, T_l);
         int done = fabs(fn - f) <= tol;
         f = fn;
         if (done) break;
@@ -596,8 +648,8 @@ static void collide_cell(const orc_sim *s, const double *f, const double *g,
         for (int i = 0; i < Q9; ++i) fpost[c * Q9 + i] = 0;
     }
     /* D2Q5, Eqs. (32), (34), (35), (37); the source is added after streaming. */
-    double sig = sigma_of(p, fl[c]);
-    double za = 1.0 / tauT_of(p, &s->d, fl[c]);
+    double sig = sigma_of(p, s->eps[c], fl[c]);
+    double za = 1.0 / tauT_of(p, &s->d, s->eps[c], fl[c]);
     double theta[Q5] = {1, za, za, p->zeta_e, p->zeta_nu};
     double n[Q5], neq[Q5], np[Q5];
     for (int a = 0; a < Q5; ++a) {
@@ -636,6 +688,123 @@ static int source_node(const orc_sim *s, int x, int y, int ex, int ey, int *sx, 
     return !out;
 }
 
+/* Heat-capacity bounds of cell c for the enthalpy iteration (sigma is
+ * linear in f_l in both modes). */
+static void sigma_pair(const orc_sim *s, long c, double *ss, double *sl)
+{
+    *ss = sigma_of(&s->p, s->eps[c], 0.0);
+    *sl = sigma_of(&s->p, s->eps[c], 1.0);
+}
+
+/* Latent source w~_i S0 of Eq. (38) through N^-1, added to g of cell c. */
+static void add_latent(orc_sim *s, long c, double S0)
+{
+    double St[Q5] = {0, 0, 0, 0, 0};
+    St[0] = S0;
+    St[3] = s->p.varpi * S0;
+    for (int i = 0; i < Q5; ++i) {
+        double v = 0;
+        for (int a = 0; a < Q5; ++a) v += s->L5.Ninv[i][a] * St[a];
+        s->gnew[c * Q5 + i] += DT * v;
+    }
+}
+
+/* R1: the source at the receiving node after streaming; a per-node fixed
+ * point (Z10). */
+static void latent_r1(orc_sim *s)
+{
+    const orc_params *p = &s->p;
+    const int nt = NT(s);
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (long c = 0; c < s->nc; ++c) {
+        double Tstar = 0;
+        for (int i = 0; i < Q5; ++i) Tstar += s->gnew[c * Q5 + i];
+        double fln, Tn, ss, sl;
+        sigma_pair(s, c, &ss, &sl);
+        s->iters[c] = orc_enthalpy(Tstar, s->fl[c], s->eps[c], p->Ste, ss, sl, cps_of(p), p->T_s,
+                                   p->T_l, p->fl_tol, p->fl_maxit, &fln, &Tn);
+        double sig = sigma_of(p, s->eps[c], fln);
+        add_latent(s, c, -(s->eps[c] / (sig * p->Ste)) * (fln - s->fl[c]) / DT); /* Eq. (38) */
+        s->flnew[c] = fln;
+    }
+}
+
+/* R2: the literal Eq. (30): the source S0(x) of a node, which needs f_l at
+ * the new time, is added to its post-collision populations before they
+ * stream, so node y receives w~_i S0(y - e_i) from each neighbour (its own
+ * S0 for i = 0 and for directions whose source lies behind a wall, whose
+ * extrapolation uses the node's own post-collision population).  The new
+ * f_l of all nodes is found together: a Jacobi iteration of Eqs. (40)-(42)
+ * over the lattice until the largest change of f_l is at most fl_tol. */
+static void latent_r2(orc_sim *s)
+{
+    const orc_params *p = &s->p;
+    const int nx = s->nx, ny = s->ny, nt = NT(s);
+    const long nc = s->nc;
+    double *f = dalloc(nc), *fn = dalloc(nc), *S0 = dalloc(nc), *Ts = dalloc(nc);
+    for (long c = 0; c < nc; ++c) {
+        double t = 0;
+        for (int i = 0; i < Q5; ++i) t += s->gnew[c * Q5 + i];
+        Ts[c] = t;
+        f[c] = s->fl[c];
+    }
+    const double w0 = (1.0 - p->varpi) / 5.0, w1 = (4.0 + p->varpi) / 20.0; /* N^-1 (1,0,0,varpi,0) */
+    int it = 0;
+    for (;;) {
+        ++it;
+#pragma omp parallel for num_threads(nt) schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            double sig = sigma_of(p, s->eps[c], f[c]);
+            S0[c] = -(s->eps[c] / (sig * p->Ste)) * (f[c] - s->fl[c]) / DT;
+        }
+        double delta = 0;
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(max : delta)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long c = (long)y * nx + x;
+                double T = Ts[c] + DT * w0 * S0[c];
+                for (int i = 1; i < Q5; ++i) {
+                    int sx, sy, side;
+                    long sc = c;
+                    if (source_node(s, x, y, s->L5.ex[i], s->L5.ey[i], &sx, &sy, &side))
+                        sc = (long)sy * nx + sx;
+                    T += DT * w1 * S0[sc];
+                }
+                double En = En_of(T, f[c], p->Ste, cps_of(p)); /* Eq. (40) */
+                fn[c] = fl_of_T(T_of_En(En, p->T_s, p->T_l, p->Ste, cps_of(p)), p->T_s, p->T_l);
+                double dd = fabs(fn[c] - f[c]);
+                if (dd > delta) delta = dd;
+            }
+        double *tmp = f;
+        f = fn;
+        fn = tmp;
+        if (delta <= p->fl_tol || it >= p->fl_maxit) break;
+    }
+    /* the streamed sources, with the converged f_l */
+    for (long c = 0; c < nc; ++c) {
+        double sig = sigma_of(p, s->eps[c], f[c]);
+        S0[c] = -(s->eps[c] / (sig * p->Ste)) * (f[c] - s->fl[c]) / DT;
+    }
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long c = (long)y * nx + x;
+            s->gnew[c * Q5 + 0] += DT * w0 * S0[c];
+            for (int i = 1; i < Q5; ++i) {
+                int sx, sy, side;
+                long sc = c;
+                if (source_node(s, x, y, s->L5.ex[i], s->L5.ey[i], &sx, &sy, &side))
+                    sc = (long)sy * nx + sx;
+                s->gnew[c * Q5 + i] += DT * w1 * S0[sc];
+            }
+            s->flnew[c] = f[c];
+            s->iters[c] = it;
+        }
+    free(f);
+    free(fn);
+    free(S0);
+    free(Ts);
+}
+
 static void one_step(orc_sim *s)
 {
     const orc_params *p = &s->p;
@@ -662,7 +831,7 @@ static void one_step(orc_sim *s)
         for (int x = 0; x < nx; ++x) {
             long c = (long)y * nx + x;
             int sx, sy, side;
-            double sig = sigma_of(p, s->fl[c]);
+            double sig = sigma_of(p, s->eps[c], s->fl[c]);
             double geq_x[Q5];
             orc_geq(s->T[c], s->ux[c], s->uy[c], sig, p->varpi, geq_x);
             for (int i = 0; i < Q5; ++i) {
@@ -696,26 +865,11 @@ static void one_step(orc_sim *s)
     }
 
     /* Step 6: iterated enthalpy method and the latent source N^-1 dt S~
-     * (Eqs. 30, 38, 40-42), at the receiving node. */
-#pragma omp parallel for num_threads(nt) schedule(static)
-    for (long c = 0; c < nc; ++c) {
-        double Tstar = 0;
-        for (int i = 0; i < Q5; ++i) Tstar += s->gnew[c * Q5 + i];
-        double fln, Tn;
-        s->iters[c] = orc_enthalpy(Tstar, s->fl[c], s->eps[c], p->Ste, p->sigma_s,
-                                   p->sigma_l, p->T_s, p->T_l, p->fl_tol, p->fl_maxit,
-                                   &fln, &Tn);
-        double sig = sigma_of(p, fln);
-        double St[Q5] = {0, 0, 0, 0, 0};
-        St[0] = -(s->eps[c] / (sig * p->Ste)) * (fln - s->fl[c]) / DT; /* Eq. (38) */
-        St[3] = p->varpi * St[0];
-        for (int i = 0; i < Q5; ++i) {
-            double v = 0;
-            for (int a = 0; a < Q5; ++a) v += s->L5.Ninv[i][a] * St[a];
-            s->gnew[c * Q5 + i] += DT * v;
-        }
-        s->flnew[c] = fln;
-    }
+     * (Eqs. 30, 38, 40-42). */
+    if (p->latent_mode == 1)
+        latent_r2(s);
+    else
+        latent_r1(s);
 
     /* Step 7: flow mask update.  A node that became liquid starts at rest,
      * f_i = w_i rho_bar, with rho_bar the mean start-of-step density of its

@@ -48,7 +48,21 @@ typedef struct {
     int fl_maxit;          /* enthalpy iteration cap                            */
     int convective;        /* vartheta of Eq. (34)                              */
     int nthreads;          /* OpenMP threads (<= 0: runtime default)            */
+    /* Variants of the thermal model (ablations of the readings):            */
+    int sigma_mode;        /* 0: sigma_s + f_l (sigma_l - sigma_s); 1: Eq. (7)  */
+    double cps_ratio;      /* c_ps / c_pl (sigma_mode 1)                        */
+    double cm_ratio;       /* (rho c_p)_m / (rho c_pl) of the matrix (mode 1)    */
+    int ke_mode;           /* 0: alpha_e linear in f_l; 1: k_e of Eq. (8)       */
+    double ks_ratio;       /* k_s / k_l (ke_mode 1)                             */
+    double km_ratio;       /* k_m / k_l of the matrix (ke_mode 1)               */
+    int latent_mode;       /* 0: source at the receiving node after streaming,
+                              per-node iteration (R1); 1: source at the pre-
+                              stream site, global iteration (R2, Eq. 30)       */
 } orc_params;
+
+/* Effective conductivity ratio k_e / k_l of Eq. (8) for porosity phi and
+ * liquid fraction fl (k_p = fl k_l + (1 - fl) k_s). */
+double orc_ke(double phi, double fl, double ks_ratio, double km_ratio);
 
 /* Lattice constants derived from orc_params (Sec. 3, Sec. 4). */
 typedef struct {
@@ -83,9 +97,10 @@ void orc_collide_f(const double *f9, double rho, double ux, double uy, double Fx
 /* Eqs. (24)-(28) and (4): velocity and total force of one cell. */
 void orc_closure(double jx, double jy, double phi, double nu_l, double Ke,
                  double Ce, double Gx, double Gy, double *u2, double *F2);
-/* Iterated enthalpy update of one cell; returns iterations used. */
+/* Iterated enthalpy update of one cell (cps = c_ps / c_pl in Eqs. 40-41);
+ * returns iterations used. */
 int orc_enthalpy(double Tstar, double fl_old, double eps, double Ste,
-                 double sigma_s, double sigma_l, double T_s, double T_l,
+                 double sigma_s, double sigma_l, double cps, double T_s, double T_l,
                  double tol, int maxit, double *fl_new, double *T_new);
 
 /* ---- whole-lattice simulation ------------------------------------------ */

@@ -38,7 +38,10 @@ class Params(C.Structure):
                 ("varpi", C.c_double), ("s_e", C.c_double), ("s_eps", C.c_double),
                 ("s_q", C.c_double), ("zeta_e", C.c_double), ("zeta_nu", C.c_double),
                 ("ergun_c", C.c_double), ("fl_tol", C.c_double),
-                ("fl_maxit", C.c_int), ("convective", C.c_int), ("nthreads", C.c_int)]
+                ("fl_maxit", C.c_int), ("convective", C.c_int), ("nthreads", C.c_int),
+                ("sigma_mode", C.c_int), ("cps_ratio", C.c_double), ("cm_ratio", C.c_double),
+                ("ke_mode", C.c_int), ("ks_ratio", C.c_double), ("km_ratio", C.c_double),
+                ("latent_mode", C.c_int)]
 
 
 class Derived(C.Structure):
@@ -69,7 +72,9 @@ def _load():
         lib.orc_neq.argtypes = [C.c_double] * 5 + [C.c_int, _DP]
         lib.orc_collide_f.argtypes = [_DP] + [C.c_double] * 6 + [_DP, _DP]
         lib.orc_closure.argtypes = [C.c_double] * 8 + [_DP, _DP]
-        lib.orc_enthalpy.argtypes = [C.c_double] * 9 + [C.c_int, _DP, _DP]
+        lib.orc_enthalpy.argtypes = [C.c_double] * 10 + [C.c_int, _DP, _DP]
+        lib.orc_ke.argtypes = [C.c_double] * 4
+        lib.orc_ke.restype = C.c_double
         lib.orc_enthalpy.restype = C.c_int
         lib.orc_create.argtypes = [C.POINTER(Params), _DP, _DP, _DP]
         lib.orc_create.restype = C.c_void_p
@@ -170,11 +175,16 @@ def closure(jx, jy, phi, nu_l, Ke, Ce, Gx, Gy):
 
 
 def enthalpy(Tstar, fl_old, eps, Ste, sigma_s=1.0, sigma_l=1.0, T_s=-0.02, T_l=0.02,
-             tol=1e-12, maxit=200):
+             tol=1e-12, maxit=200, cps=1.0):
     fl = C.c_double(); T = C.c_double()
-    it = _load().orc_enthalpy(Tstar, fl_old, eps, Ste, sigma_s, sigma_l, T_s, T_l, tol,
+    it = _load().orc_enthalpy(Tstar, fl_old, eps, Ste, sigma_s, sigma_l, cps, T_s, T_l, tol,
                               maxit, C.byref(fl), C.byref(T))
     return fl.value, T.value, it
+
+
+def ke(phi, fl, ks_ratio, km_ratio):
+    """k_e / k_l from Eq. (8)."""
+    return _load().orc_ke(phi, fl, ks_ratio, km_ratio)
 
 
 class OracleSim:
