@@ -92,6 +92,26 @@ typedef struct {
     int32_t block_rows; /* rows per step-kernel block: 4 or 8; 0 = 4                   */
     int32_t cells_per_lane; /* nodes per lane in the step kernel: 1 or 2; 0 = 1       */
     void *stream;       /* hipStream_t for all work; NULL = null stream                 */
+    /* Literal variants of the thermal model (single lattices only; the batch
+     * and the adjoint reject them with DMRT_EINVAL):                          */
+    int32_t sigma_mode; /* 0: sigma = sigma_s + f_l (sigma_l - sigma_s); 1: sigma of each
+                           node from Eq. (7), phi (f_l + (1 - f_l) cps_ratio) + (1 - phi)
+                           cm_ratio, with cps_ratio also in the enthalpy of
+                           Eqs. (40)-(41) (c_p = f_l + (1 - f_l) cps_ratio,
+                           En_s = cps_ratio T_s); default 0                    */
+    int32_t ke_mode;    /* 0: alpha_e = lambda (alpha_l f_l + alpha_s (1 - f_l));
+                           1: alpha_e = alpha_l k_e / k_l with k_e the root of Eq. (8)
+                           for the node's porosity, k_p = f_l + (1 - f_l) ks_ratio,
+                           k_m = km_ratio (lambda, alpha_ratio unused); default 0 */
+    int32_t latent_mode;/* 0: latent source after streaming at the receiving node,
+                           per-node iteration (R1); 1: source added before streaming
+                           (Eq. 30), f_l of all nodes iterated together (R2);
+                           default 0                                           */
+    int32_t reserved;   /* 0                                                    */
+    double cps_ratio;   /* c_ps / c_pl (sigma_mode 1), 1                        */
+    double cm_ratio;    /* (rho c_p)_m / (rho c_pl) of the matrix (sigma_mode 1), 1 */
+    double ks_ratio;    /* k_s / k_l (ke_mode 1), 1                             */
+    double km_ratio;    /* k_m / k_l of the matrix (ke_mode 1), 1               */
 } dmrt_opts;
 
 /* Lattice constants derived from the dimensionless inputs (Sec. 4.3). */

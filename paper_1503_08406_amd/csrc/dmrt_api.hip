@@ -75,6 +75,10 @@ struct dmrt {
     float* stage = nullptr;   // two packed nx*ny planes: terminal adjoints in, gradients out
     hipGraphExec_t adj_graph = nullptr;  // the reversed pass for rec_cap steps
     bool adj_flow = false;
+    // latent source at the pre-stream site: T*, two f_l iterates, sweep flags
+    bool r2 = false;
+    char* r2_base = nullptr;
+    dmrtk::R2Bufs R{};
 };
 
 namespace {
@@ -134,6 +138,12 @@ int check_opts(const dmrt_opts& o)
         return fail(DMRT_EINVAL, "block_rows must be 0, 4 or 8");
     if (o.cells_per_lane < 0 || o.cells_per_lane > 2)
         return fail(DMRT_EINVAL, "cells_per_lane must be 0, 1 or 2");
+    if (o.sigma_mode < 0 || o.sigma_mode > 1 || o.ke_mode < 0 || o.ke_mode > 1 ||
+        o.latent_mode < 0 || o.latent_mode > 1)
+        return fail(DMRT_EINVAL, "sigma_mode, ke_mode and latent_mode must be 0 or 1");
+    if (!finite_pos(o.cps_ratio) || !finite_pos(o.cm_ratio) || !finite_pos(o.ks_ratio) ||
+        !finite_pos(o.km_ratio))
+        return fail(DMRT_EINVAL, "cps_ratio, cm_ratio, ks_ratio, km_ratio must be > 0");
     return DMRT_OK;
 }
 
@@ -176,9 +186,19 @@ void fill_phys(Phys& P, const dmrt_derived& d, double Ste, const dmrt_opts& o)
     P.fl_tol = (float)o.fl_tol;
     P.fl_maxit = o.fl_maxit;
     P.conv = o.convective ? 1.0f : 0.0f;
-    P.zeta_uniform = (o.alpha_ratio == 1.0 && o.sigma_s == o.sigma_l) ? 1 : 0;
+    P.zeta_uniform =
+        (o.alpha_ratio == 1.0 && o.sigma_s == o.sigma_l && !o.sigma_mode && !o.ke_mode) ? 1 : 0;
     P.zeta_a = (float)(1.0 / d.tau_T_liquid);
     P.T_init = (float)o.T_init;
+    P.sig_mode = o.sigma_mode;
+    P.cps = (float)o.cps_ratio;
+    P.cm = (float)o.cm_ratio;
+    P.Es = (float)(o.cps_ratio * o.T_s);
+    P.inv_den_c = (float)(1.0 / (o.T_l + 1.0 / Ste - o.cps_ratio * o.T_s));
+    P.ke_mode = o.ke_mode;
+    P.ks = (float)o.ks_ratio;
+    P.km = (float)o.km_ratio;
+    P.alpha_l = (float)d.alpha_l;
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -199,7 +219,9 @@ void fill_geom(Geom& G, int nx, int ny, const dmrt_bc& bc, const dmrt_opts& o)
         G.T_wall[k] = (float)bc.T_wall[k];
     }
     G.block_rows = o.block_rows ? o.block_rows : 4;
-    G.cells_per_lane = o.cells_per_lane ? o.cells_per_lane : 1;
+    // the thermal-model variants run one node per lane
+    const bool variant = o.sigma_mode || o.ke_mode || o.latent_mode;
+    G.cells_per_lane = (o.cells_per_lane && !variant) ? o.cells_per_lane : 1;
     // 32-bit buffer addressing while the largest array (9 planes) fits 4 GB
     G.wide = (uint64_t)G.plane * 4 * dmrtk::FQ >= (1ull << 32) ? 1 : 0;
     set_step_tiling(G);
@@ -251,6 +273,8 @@ dmrtk::StepBufs bufs(dmrt* h, bool counted)
     B.Bc = h->Bc;
     B.it_sum = counted ? h->it_sum : nullptr;
     B.it_max = counted ? h->it_max : nullptr;
+    B.r2f = nullptr;
+    B.r2_its = 0;
     return B;
 }
 
@@ -265,10 +289,17 @@ int ensure_scratch(dmrt* h, size_t bytes)
     return DMRT_OK;
 }
 
-// One plain step launch; flips the buffer index.
+// The launches of one step from buffer parity h->cur.
+hipError_t enqueue_step(dmrt* h, bool counted)
+{
+    if (h->r2) return dmrtk::launch_step_r2(h->G, h->P, bufs(h, counted), h->R, h->flow, counted, h->stream);
+    return dmrtk::launch_step(h->G, h->P, bufs(h, counted), h->flow, counted, h->stream);
+}
+
+// One plain step; flips the buffer index.
 int step_once(dmrt* h, bool counted)
 {
-    HIPCHK(dmrtk::launch_step(h->G, h->P, bufs(h, counted), h->flow, counted, h->stream));
+    HIPCHK(enqueue_step(h, counted));
     h->cur = 1 - h->cur;
     h->t += 1;
     return DMRT_OK;
@@ -282,7 +313,7 @@ int build_graph(dmrt* h, int p)
     h->cur = p;
     HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < h->graph_steps; ++k) {
-        hipError_t e = dmrtk::launch_step(h->G, h->P, bufs(h, false), h->flow, false, h->stream);
+        hipError_t e = enqueue_step(h, false);
         h->cur = 1 - h->cur;
         if (e != hipSuccess) {
             hipGraph_t gdrop;
@@ -438,6 +469,8 @@ int enqueue_adjoint(dmrt* h)
             B.Ac = h->Ac;
             B.Bc = h->Bc;
             B.it_sum = B.it_max = nullptr;
+            B.r2f = nullptr;
+            B.r2_its = 0;
             hipError_t e = dmrtk::launch_step(G, h->P, B, h->flow, false, h->stream);
             if (e != hipSuccess) return fail(DMRT_EDEVICE, "recompute launch: %s", hipGetErrorString(e));
         }
@@ -508,6 +541,14 @@ void dmrt_opts_default(dmrt_opts* o)
     o->block_rows = 0;
     o->cells_per_lane = 0;
     o->stream = nullptr;
+    o->sigma_mode = 0;
+    o->ke_mode = 0;
+    o->latent_mode = 0;
+    o->reserved = 0;
+    o->cps_ratio = 1.0;
+    o->cm_ratio = 1.0;
+    o->ks_ratio = 1.0;
+    o->km_ratio = 1.0;
 }
 
 int dmrt_derive(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
@@ -532,6 +573,8 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     int rc = derive_impl(grid, Ra, Da, Pr, Ste, o, &d);
     if (rc) return rc;
     if ((rc = check_opts(o)) || (rc = check_bc(bc))) return rc;
+    if (o.sigma_mode && !(o.T_l + 1.0 / Ste > o.cps_ratio * o.T_s))
+        return fail(DMRT_EINVAL, "sigma_mode 1 needs T_l + 1/St > cps_ratio T_s");
     const long long nx = grid->nx, ny = grid->ny;
     const long long pitch = (nx + 63) / 64 * 64;
     if (ny * pitch >= (1ll << 31)) return fail(DMRT_EINVAL, "lattice too large (%lld x %lld)", nx, ny);
@@ -593,6 +636,22 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     if (e == hipSuccess) e = hipMemcpyAsync(h->Bc, pb.data(), pcell * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "upload: %s", hipGetErrorString(e)));
+
+    if (o.latent_mode) {
+        // T*, two f_l iterates and the sweep flags of the global iteration
+        const size_t r2_bytes = 3 * plane_b + align256((size_t)o.fl_maxit * sizeof(int));
+        e = hipMalloc(&h->r2_base, r2_bytes);
+        if (e != hipSuccess)
+            return bail(fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE,
+                             "hipMalloc(%zu): %s", r2_bytes, hipGetErrorString(e)));
+        h->r2 = true;
+        h->R.ts = (float*)h->r2_base;
+        h->R.r2a = (float*)(h->r2_base + plane_b);
+        h->R.r2b = (float*)(h->r2_base + 2 * plane_b);
+        h->R.flags = (int*)(h->r2_base + 3 * plane_b);
+        e = hipMemsetAsync(h->r2_base, 0, r2_bytes, h->stream);
+        if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "memset: %s", hipGetErrorString(e)));
+    }
 
     // Initial state: uniform T_init at rest.
     if ((rc = dmrt_set_state(h, nullptr, nullptr, nullptr))) return bail(rc);
@@ -813,8 +872,9 @@ int dmrt_record(dmrt_t* h, int64_t n)
 {
     if (!h) return fail(DMRT_EINVAL, "null handle");
     if (n < 1) return fail(DMRT_EINVAL, "record at least one step");
-    if (h->P.dsig != 0.0f || !h->P.zeta_uniform)
-        return fail(DMRT_EINVAL, "the adjoint needs uniform sigma and tau_T (sigma_s == sigma_l, alpha_ratio == 1)");
+    if (h->P.dsig != 0.0f || !h->P.zeta_uniform || h->P.sig_mode || h->P.ke_mode || h->r2)
+        return fail(DMRT_EINVAL, "the adjoint needs uniform sigma and tau_T (sigma_s == sigma_l, "
+                                 "alpha_ratio == 1, no thermal-model variant)");
     HIPCHK(hipSetDevice(h->dev));
     int64_t S = 1;
     while (S * S < n) ++S;
@@ -933,6 +993,7 @@ void dmrt_destroy(dmrt_t* h)
     if (h->base) (void)hipFree(h->base);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->it_sum) (void)hipFree(h->it_sum);
+    if (h->r2_base) (void)hipFree(h->r2_base);
     drop_recording(h);
     delete h;
 }
@@ -1166,6 +1227,8 @@ int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opt
     if (opts) o = *opts; else dmrt_opts_default(&o);
     int rc = check_opts(o);
     if (rc) return rc;
+    if (o.sigma_mode || o.ke_mode || o.latent_mode)
+        return fail(DMRT_EINVAL, "the thermal-model variants are for single lattices only");
 
     dmrt_batch* b = new (std::nothrow) dmrt_batch;
     if (!b) return fail(DMRT_ENOMEM, "host allocation");

@@ -56,6 +56,8 @@ __global__ __launch_bounds__(TX * TYB) void k_batch_step(BatchArgs a)
         B.uin = nullptr;
         B.eps = B.Ac = B.Bc = nullptr;
         B.it_sum = B.it_max = nullptr;
+        B.r2f = nullptr;
+        B.r2_its = 0;
         Arrays<BufIO> A(G, B);
         A.eps_u = C.eps;
         A.Ac_u = C.Ac;

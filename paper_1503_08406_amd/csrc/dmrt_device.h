@@ -199,23 +199,62 @@ __device__ __forceinline__ void flow_collide(float (&d)[9], float fl1, float eps
     d[8] -= cd + X2 - Y2 - Qq;
 }
 
-// zeta_alpha = 1/tau_T(f_l) with tau_T = 1/2 + alpha_e(f_l)/(sigma c_sT^2).
-__device__ __forceinline__ float zeta_alpha(const Phys& P, float fl, float isig)
+// Heat-capacity ratio of a node, sigma(f_l) = s0 + f_l ds: the uniform
+// pair, or Eq. (7) with the node's porosity (rho_s = rho_l).  VAR = false
+// compiles the default model only.
+template <bool VAR>
+__device__ __forceinline__ void node_sigma(const Phys& P, float eps, float& s0, float& ds)
+{
+    if (VAR && P.sig_mode) {
+        s0 = eps * P.cps + (1.0f - eps) * P.cm;
+        ds = eps * (1.0f - P.cps);
+    } else {
+        s0 = P.sig_s;
+        ds = P.dsig;
+    }
+}
+
+// k_e / k_l of Eq. (8).  With z = k_e^(1/3) the equation is the cubic
+// z^3 + p z - k_m = 0, p = phi (k_m - k_p) / k_p^(1/3), k_p = f_l + (1 - f_l)
+// k_s; k_e lies between k_m and k_p, and from z = cbrt(max(k_m, k_p)), where
+// the cubic is non-negative and convex, Newton's method descends
+// monotonically to the largest root.
+__device__ __forceinline__ float ke_ratio(const Phys& P, float phi, float fl)
+{
+    const float kp = fl + (1.0f - fl) * P.ks;
+    const float p = phi * (P.km - kp) / cbrtf(kp);
+    float z = cbrtf(fmaxf(P.km, kp));
+    for (int i = 0; i < 32; ++i) {
+        const float dz = ((z * z + p) * z - P.km) / (3.0f * z * z + p);
+        z -= dz;
+        if (!(fabsf(dz) > 1e-7f * z)) break;
+    }
+    return z * z * z;
+}
+
+// zeta_alpha = 1/tau_T(f_l) with tau_T = 1/2 + alpha_e(f_l)/(sigma c_sT^2);
+// alpha_e = lambda alpha(f_l), linear between the phases, or alpha_l k_e /
+// k_l (Eq. 8) with the node's porosity eps.
+template <bool VAR>
+__device__ __forceinline__ float zeta_alpha(const Phys& P, float fl, float isig, float eps)
 {
     if (P.zeta_uniform) return P.zeta_a;
+    if (VAR && P.ke_mode)
+        return frcp(0.5f + P.alpha_l * ke_ratio(P, eps, fl) * isig * P.inv_csT2);
     return frcp(0.5f + (P.lam_as + fl * P.dlam) * isig * P.inv_csT2);
 }
 
 // D2Q5 MRT collision (Eqs. 32, 34, 35, 37) with temperature T1 and
-// 1/sigma = isig.
+// 1/sigma = isig at a node of porosity eps.
+template <bool VAR>
 __device__ __forceinline__ void thermal_collide(float (&g)[5], float fl1, float isig, float T1,
-                                                float ux, float uy, const Phys& P)
+                                                float ux, float uy, float eps, const Phys& P)
 {
     const float n1 = g[1] - g[3], n2 = g[2] - g[4];
     const float s13 = g[1] + g[3], s24 = g[2] + g[4];
     const float n3 = (s13 + s24) - 4.0f * g[0];
     const float n4 = s13 - s24;
-    const float za = zeta_alpha(P, fl1, isig);
+    const float za = zeta_alpha<VAR>(P, fl1, isig, eps);
     const float ct = P.conv * T1 * isig;
     const float D1 = za * (n1 - ct * ux), D2 = za * (n2 - ct * uy);
     const float D3 = P.zeta_e * (n3 - P.varpi * T1), D4 = P.zeta_nu * n4;

@@ -35,6 +35,12 @@ struct Phys {
     int zeta_uniform;             // 1 when zeta_alpha does not depend on f_l
     float zeta_a;                 // that uniform zeta_alpha
     float T_init;
+    // literal variants of the thermal model (0 = the default readings)
+    int sig_mode;                 // 1: sigma of each node from Eq. (7)
+    float cps, cm;                // c_ps / c_pl, (rho c_p)_m / (rho c_pl)
+    float Es, inv_den_c;          // c_ps T_s, 1 / (T_l + 1/St - c_ps T_s)
+    int ke_mode;                  // 1: alpha_e = alpha_l k_e / k_l with k_e of Eq. (8)
+    float ks, km, alpha_l;        // k_s / k_l, k_m / k_l, alpha_l
 };
 
 // Lattice geometry and boundary description.
@@ -71,10 +77,27 @@ struct StepBufs {
     const float* __restrict__ Bc;  // phi F_eps / (sqrt(K) (1-phi)): Forchheimer
     int* __restrict__ it_sum;      // enthalpy-iteration counters (counted mode)
     int* __restrict__ it_max;
+    const float* __restrict__ r2f; // R2: f_l^{k+1} from the global iteration
+    int r2_its;                    // R2: its sweeps
 };
 
 hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flow,
                        bool counted, hipStream_t s);
+
+// One step with the latent source at the pre-stream site (R2): T* of every
+// node (ts), at most P.fl_maxit Jacobi sweeps of f_l over the lattice
+// (iterates in r2a / r2b; flags[j] = 1 when sweep j changed some f_l by more
+// than P.fl_tol, and a sweep after an unchanged one does nothing), then the
+// step kernel with the converged f_l.  ts, r2a, r2b: one plane each;
+// flags: P.fl_maxit ints.
+struct R2Bufs {
+    float* ts;
+    float* r2a;
+    float* r2b;
+    int* flags;
+};
+hipError_t launch_step_r2(const Geom& G, const Phys& P, const StepBufs& B, const R2Bufs& R,
+                          bool flow, bool counted, hipStream_t s);
 
 // One cavity of a batch: its lattice, its model constants, its uniform
 // porous fields and the element offsets of its planes in the shared arenas.

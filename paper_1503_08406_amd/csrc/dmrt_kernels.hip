@@ -63,7 +63,9 @@ __global__ __launch_bounds__(TX * TY) void k_load_state(Geom G, Phys P, const fl
         uxb[c] = ux;
         uyb[c] = uy;
     }
-    thermal_collide(g, fl, frcp(P.sig_s + fl * P.dsig), T, ux, uy, P);
+    float sg0, dsg;
+    node_sigma<true>(P, eps, sg0, dsg);
+    thermal_collide<true>(g, fl, frcp(sg0 + fl * dsg), T, ux, uy, eps, P);
 #pragma unroll
     for (int i = 0; i < 5; ++i) gcur[i * pl + c] = g[i];
     flcur[c] = fl;
@@ -165,7 +167,9 @@ __global__ __launch_bounds__(TX * TY) void k_diag(Geom G, Phys P, const float* f
             }
             mass = r;
         }
-        const double sig = (double)P.sig_s + (double)fl * P.dsig;
+        float sg0, dsg;
+        node_sigma<true>(P, eps, sg0, dsg);
+        const double sig = (double)sg0 + (double)fl * dsg;
         v[0] = mass;
         v[1] = sig * T + (double)eps * fl * P.inv_St;
         v[2] = fl;

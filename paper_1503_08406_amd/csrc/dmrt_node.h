@@ -96,32 +96,88 @@ __device__ __forceinline__ void node_load(const Geom& G, const Arrays<IO>& A, in
     }
 }
 
-// Thermal part of the step before the flow: wall sources of g (Eq. 36 with
-// non-equilibrium extrapolation), the iterated enthalpy update (Eqs. 38,
-// 40-42) and the latent source added to g.  Gives T^{k+1}, f_l^{k+1} and
-// 1/sigma(f_l^{k+1}).
-template <class IO, bool FLOW, bool COUNT>
-__device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, const StepBufs& B,
-                                              const Arrays<IO>& A, Node<IO>& n, float& T1,
-                                              float& fl1, float& isig1)
+// Thermal models of the node functions: the default readings, the literal
+// variants of sigma (Eq. 7) and k_e (Eq. 8), and the last pass of a step
+// with the latent source at the pre-stream site (R2, with f_l^{k+1} from a
+// global iteration that ran before).
+enum { TM_DEFAULT = 0, TM_VARIANT = 1, TM_R2 = 2 };
+
+// Wall sources of g (Eq. 36 with non-equilibrium extrapolation) from the
+// start-of-step values of a wall node; sigma(f_l^k) = sg0 + f_l^k dsg.
+template <class IO, bool FLOW>
+__device__ __forceinline__ void node_wall_g(const Geom& G, const Phys& P, Node<IO>& n, float sg0,
+                                            float dsg)
 {
     const bool wxm = (n.x == 0) & !G.per_x, wxp = (n.x == G.nx - 1) & !G.per_x;
     const bool wym = (n.y == 0) & !G.per_y, wyp = (n.y == G.ny - 1) & !G.per_y;
-    const float flk = n.flk, eps = n.eps;
-    float (&g)[5] = n.g;
-
-    // ---- wall sources of g (start-of-step values of this node)
     if (wxm | wxp | wym | wyp) {
+        const float flk = n.flk;
+        float (&g)[5] = n.g;
         const bool liqk = FLOW && flk > 0.0f;
         const float uxk = liqk ? n.uk[0] : 0.0f, uyk = liqk ? n.uk[1] : 0.0f;
         const float q1 = n.q[0], q2 = n.q[1], q3 = n.q[2], q4 = n.q[3];
         const float Tk = g[0] + ((q1 + q3) + (q2 + q4));
-        const float cu = frcp((P.sig_s + flk * P.dsig) * P.csT2);
+        const float cu = frcp((sg0 + flk * dsg) * P.csT2);
         const float wTk = P.w5_1 * Tk;
         if (wxm) g[1] = P.w5_1 * (G.wall_T[0] ? G.T_wall[0] : Tk) + q1 - wTk * (1.0f + uxk * cu);
         if (wym) g[2] = P.w5_1 * (G.wall_T[2] ? G.T_wall[2] : Tk) + q2 - wTk * (1.0f + uyk * cu);
         if (wxp) g[3] = P.w5_1 * (G.wall_T[1] ? G.T_wall[1] : Tk) + q3 - wTk * (1.0f - uxk * cu);
         if (wyp) g[4] = P.w5_1 * (G.wall_T[3] ? G.T_wall[3] : Tk) + q4 - wTk * (1.0f - uyk * cu);
+    }
+}
+
+// S~_0 dt of Eq. (38) at a node of porosity eps whose f_l goes from fk to f1.
+template <bool VAR>
+__device__ __forceinline__ float latent_S0(const Phys& P, float eps, float fk, float f1)
+{
+    float s0, ds;
+    node_sigma<VAR>(P, eps, s0, ds);
+    return -(eps * P.inv_St) * (f1 - fk) * frcp(s0 + f1 * ds);
+}
+
+// Thermal part of the step before the flow: wall sources of g, then the
+// enthalpy update and the latent source added to g.  Gives T^{k+1},
+// f_l^{k+1} and 1/sigma(f_l^{k+1}).
+//   R1 (TM_DEFAULT, TM_VARIANT): iterated enthalpy update at the receiving
+//     node (Eqs. 38, 40-42), its source w~_i S~_0 added to every g_i.
+//   TM_R2: f_l^{k+1} of every node is given (B.r2f); each pulled g_i
+//     receives w~_i S~_0 of its pre-stream site x - e_i (Eq. 30; the node
+//     itself for i = 0 and behind a wall).
+template <class IO, bool FLOW, bool COUNT, int TM = TM_DEFAULT>
+__device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, const StepBufs& B,
+                                              const Arrays<IO>& A, Node<IO>& n, float& T1,
+                                              float& fl1, float& isig1)
+{
+    constexpr bool VAR = TM != TM_DEFAULT;
+    const float flk = n.flk, eps = n.eps;
+    float (&g)[5] = n.g;
+    float sg0, dsg;  // sigma(f_l) = sg0 + f_l dsg at this node
+    node_sigma<VAR>(P, eps, sg0, dsg);
+    node_wall_g<IO, FLOW>(G, P, n, sg0, dsg);
+
+    if constexpr (TM == TM_R2) {
+        using off_t = typename IO::off_t;
+        const IO f1v(B.r2f, (uint64_t)A.pb);
+        const off_t src[4] = {n.o1, n.o2, n.o3, n.o4};
+        float f1s[4], fks[4], es[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f1s[i] = f1v.ld(src[i], 0);
+            fks[i] = A.flin.ld(src[i], 0);
+            es[i] = A.stat.ld(src[i], 0);
+        }
+        fl1 = f1v.ld(n.o, 0);
+        g[0] += P.w5_0 * latent_S0<true>(P, eps, flk, fl1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g[i + 1] += P.w5_1 * latent_S0<true>(P, es[i], fks[i], f1s[i]);
+        T1 = g[0] + ((g[1] + g[3]) + (g[2] + g[4]));
+        isig1 = frcp(sg0 + fl1 * dsg);
+        if (COUNT) {
+            const size_t ci = (size_t)n.y * G.pitch + n.x;
+            B.it_sum[ci] += B.r2_its;
+            if (B.r2_its > B.it_max[ci]) B.it_max[ci] = B.r2_its;
+        }
+        return;
     }
 
     // ---- iterated enthalpy update at the receiving node; the wavefront
@@ -130,7 +186,20 @@ __device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, cons
     const float alat = eps * P.inv_St;  // phi L_a / c_p
     float f = flk;
     int it = 0;
-    if (P.dsig == 0.0f) {
+    if (VAR && P.sig_mode) {
+        // Eq. (7) sigma of this node; Eq. (40) with the mixture c_p and
+        // Eq. (41) with En_s = c_ps T_s
+        const float dcp = 1.0f - P.cps;
+        for (;;) {
+            ++it;
+            const float T = Tstar - alat * (f - flk) * frcp(sg0 + f * dsg);
+            const float En = (P.cps + f * dcp) * T + f * P.inv_St;
+            const float fn = fminf(fmaxf((En - P.Es) * P.inv_den_c, 0.0f), 1.0f);
+            const bool done = fabsf(fn - f) <= P.fl_tol || it >= P.fl_maxit;
+            f = fn;
+            if (done) break;
+        }
+    } else if (P.dsig == 0.0f) {
         const float a = alat * P.isig_s;
         for (;;) {
             ++it;
@@ -151,7 +220,8 @@ __device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, cons
         }
     }
     fl1 = f;
-    isig1 = P.dsig == 0.0f ? P.isig_s : frcp(P.sig_s + fl1 * P.dsig);
+    isig1 = (VAR && P.sig_mode) ? frcp(sg0 + fl1 * dsg)
+                                : P.dsig == 0.0f ? P.isig_s : frcp(P.sig_s + fl1 * P.dsig);
     const float dT = -alat * (fl1 - flk) * isig1;  // S~_0 (Eq. 38)
     T1 = Tstar + dT;
     g[0] += P.w5_0 * dT;
@@ -288,26 +358,26 @@ __device__ __forceinline__ void node_flow(const Geom& G, const Phys& P, const Ar
 }
 
 // D2Q5 MRT collision (Eqs. 35, 37) and the stores of g+ and f_l^{k+1}.
-template <class IO>
+template <class IO, int TM = TM_DEFAULT>
 __device__ __forceinline__ void node_thermal(const Phys& P, const Arrays<IO>& A, Node<IO>& n,
                                              float fl1, float isig1, float T1, float ux, float uy)
 {
     using off_t = typename IO::off_t;
-    thermal_collide(n.g, fl1, isig1, T1, ux, uy, P);
+    thermal_collide<TM != TM_DEFAULT>(n.g, fl1, isig1, T1, ux, uy, n.eps, P);
 #pragma unroll
     for (int i = 0; i < 5; ++i) A.gout.st(n.o, (off_t)i * A.pb, n.g[i]);
     A.flout.st(n.o, 0, fl1);
 }
 
 // The rest of the step of one node, without handing work to other lanes.
-template <class IO, bool FLOW, bool COUNT, bool USTAT = false>
+template <class IO, bool FLOW, bool COUNT, bool USTAT = false, int TM = TM_DEFAULT>
 __device__ __forceinline__ void node_finish(const Geom& G, const Phys& P, const StepBufs& B,
                                             const Arrays<IO>& A, Node<IO>& n)
 {
     float T1, fl1, isig1, ux = 0.0f, uy = 0.0f;
-    node_enthalpy<IO, FLOW, COUNT>(G, P, B, A, n, T1, fl1, isig1);
+    node_enthalpy<IO, FLOW, COUNT, TM>(G, P, B, A, n, T1, fl1, isig1);
     if (FLOW && fl1 > 0.0f) node_flow<IO, USTAT>(G, P, A, n.x, n.y, n.flk, fl1, T1, n.eps, ux, uy);
-    node_thermal(P, A, n, fl1, isig1, T1, ux, uy);
+    node_thermal<IO, TM>(P, A, n, fl1, isig1, T1, ux, uy);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,7 +418,7 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long m, int j)
 // One node per lane of a 64 x (NT/64) block; every lane of the block must
 // call this (valid = false for lanes outside the lattice).  `parity`
 // alternates between consecutive tiles of a block that reuses S.
-template <class IO, bool FLOW, bool COUNT, bool USTAT, int NT>
+template <class IO, bool FLOW, bool COUNT, bool USTAT, int NT, int TM = TM_DEFAULT>
 __device__ __forceinline__ void block_step(const Geom& G, const Phys& P, const StepBufs& B,
                                            const Arrays<IO>& A, int x, int y, bool valid,
                                            FlowStage<NT>& S, int parity)
@@ -360,7 +430,7 @@ __device__ __forceinline__ void block_step(const Geom& G, const Phys& P, const S
     float T1 = 0.0f, fl1 = 0.0f, isig1 = 0.0f, ux = 0.0f, uy = 0.0f;
     if (valid) {
         node_load<IO, FLOW, USTAT>(G, A, x, y, n);
-        node_enthalpy<IO, FLOW, COUNT>(G, P, B, A, n, T1, fl1, isig1);
+        node_enthalpy<IO, FLOW, COUNT, TM>(G, P, B, A, n, T1, fl1, isig1);
     }
     if (FLOW) {
         const bool act = valid && fl1 > 0.0f;
@@ -402,7 +472,7 @@ __device__ __forceinline__ void block_step(const Geom& G, const Phys& P, const S
             }
         }
     }
-    if (valid) node_thermal(P, A, n, fl1, isig1, T1, ux, uy);
+    if (valid) node_thermal<IO, TM>(P, A, n, fl1, isig1, T1, ux, uy);
 }
 
 }  // namespace dmrtk
