@@ -186,6 +186,75 @@ def adjoint_timing(warm=200):
             "liquid_cells_end": int((F["fl"] > 0).sum())}
 
 
+# Literal readings of the thermal model against the default ones, on the
+# paper's own Sec. 4.3 problem (gallium in glass beads, 200 x 200).  The
+# ratios are fitted to the values the paper quotes there: Eq. (7) with
+# c_ps/c_pl and the matrix capacity that give sigma = 0.8604 (liquid) and
+# 0.8352 (solid) at porosity 0.385, Eq. (8) with k_s = k_l and the matrix
+# conductivity that gives lambda = k_e/k_l = 0.2719 in the liquid.
+CPS_GA, CM_GA = 0.9345454545, 0.7730081301
+KM_GA = 0.0299507727
+ABLATION = [
+    ("default", {}),
+    ("sigma_eq7", dict(sigma_mode=1, cps_ratio=CPS_GA, cm_ratio=CM_GA)),
+    ("ke_eq8", dict(ke_mode=1, ks_ratio=1.0, km_ratio=KM_GA)),
+    ("r2", dict(latent_mode=1)),
+    ("all_literal", dict(sigma_mode=1, cps_ratio=CPS_GA, cm_ratio=CM_GA, ke_mode=1, ks_ratio=1.0,
+                         km_ratio=KM_GA, latent_mode=1)),
+]
+
+
+def ablation(horizons=((0.04, True), (0.457, True), (1.829, False)), graph_steps=64):
+    """Run every reading to each Fourier number of `horizons` (the R2
+    readings only where the flag says so) and print one JSON line per
+    (reading, Fo): time per step, melted fraction, the front (mean, top and
+    bottom rows), the range of T, and the largest differences of T and f_l
+    from the default readings."""
+    import numpy as np
+    import torch
+    from paper_1503_08406_amd import workloads as W
+    from paper_1503_08406_amd.dmrt import Solver
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from conftest import front_rows
+
+    torch.cuda.set_device(0)
+    case = W.gallium_cavity()
+    ref = {}
+    for fo, with_r2 in horizons:
+        steps = W.gallium_fourier_steps(case, fo)
+        for name, over in ABLATION:
+            if over.get("latent_mode") and not with_r2:
+                continue  # R2 sweeps the whole lattice many times a step
+            s = Solver(case, graph_steps=graph_steps, **over)
+            s.step(graph_steps)  # graph capture outside the timing
+            s.sync()
+            t = time.perf_counter()
+            s.step(steps - graph_steps)
+            s.sync()
+            el = time.perf_counter() - t
+            F = s.fields()
+            d = s.diag()
+            fr = front_rows(F["fl"])
+            row = {"reading": name, "Fo": fo, "steps": steps,
+                   "us_per_step": round(el * 1e6 / (steps - graph_steps), 2),
+                   "melted": round(float(F["fl"].mean()), 5),
+                   "front_mean": round(float(fr.mean()), 3),
+                   "front_top": round(float(fr[-10:].mean()), 3),
+                   "front_bottom": round(float(fr[:10].mean()), 3),
+                   "T_min": round(float(F["T"].min()), 4), "T_max": round(float(F["T"].max()), 4),
+                   "u_max": float("%.4g" % d["u_max"]), "nonfinite": int(d["nonfinite"])}
+            if name == "default":
+                ref[fo] = F
+            else:
+                R = ref[fo]
+                row["dT_max"] = float("%.4g" % np.abs(F["T"] - R["T"]).max())
+                row["dfl_max"] = float("%.4g" % np.abs(F["fl"] - R["fl"]).max())
+                row["dfront_mean"] = round(float(np.abs(fr - front_rows(R["fl"])).mean()), 3)
+            print(json.dumps(row), flush=True)
+            s.close()
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,11 +274,16 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the benchmark: the readings of the thermal model on "
+                         "the paper's Sec. 4.3 problem, one JSON line each")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         return 2
+    if args.ablation:
+        return ablation()
 
     import torch
     from paper_1503_08406_amd import workloads as W

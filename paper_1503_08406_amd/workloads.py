@@ -84,6 +84,32 @@ def cavity(nx=1024, ny=1024, steps=100000, Ra=1e6, Da=1e-4, Pr=1.0, Ste=1.0,
                      T_l=THETA_M_CAVITY + 0.02, convective=1)
 
 
+def gallium_cavity(n=200, steps=0):
+    """The Sec. 4.3 problem as the paper sets it up (gallium melting in a
+    cavity packed with glass beads): n x n lattice, H = n, Ra = 8.409e5,
+    Da = 1.37e-5, porosity 0.385, J = 1, Pr = 0.0208, lambda = 0.2719,
+    alpha_l/alpha_s = 1, St = 0.1241, sigma 0.8604 (liquid) and 0.8352
+    (solid), Ma = 0.1; hot wall 45, cold wall and initial state 20, melting
+    at 29.78, scaled to theta = (T - 20)/25 (T_0 = 20: theta_0 = 0), with a
+    +-0.02 mushy range in theta; uniform K = Da H^2."""
+    return make_case("gallium_cavity", n, n, [WALL_T, WALL_T, WALL_ADIABATIC, WALL_ADIABATIC],
+                     [1.0, 0.0, 0.0, 0.0], Ra=8.409e5, Da=1.37e-5, Pr=0.0208, Ste=0.1241,
+                     eps=0.385, steps=steps, H=float(n), T_init=0.0,
+                     T_s=THETA_M_CAVITY - 0.02, T_l=THETA_M_CAVITY + 0.02, T0=0.0,
+                     convective=1, Ma=0.1, J=1.0, sigma_s=0.8352, sigma_l=0.8604,
+                     **{"lambda": 0.2719})
+
+
+def gallium_fourier_steps(case, fo):
+    """Time steps for Fourier number fo = t alpha_l / H^2 of a
+    gallium_cavity case (alpha_l from Ra, Pr, Ma and H as in Sec. 4.3)."""
+    H, Ra, Pr = case["H"], case["Ra"], case["Pr"]
+    Ma, J = case["opts"]["Ma"], case["opts"]["J"]
+    tau_nu = 0.5 + Ma * J * H * math.sqrt(3.0 * Pr) / math.sqrt(Ra)
+    alpha_l = (tau_nu - 0.5) / 3.0 / J / Pr
+    return int(round(fo * H * H / alpha_l))
+
+
 CAVITY_BATCH_OPTS = dict(T_init=0.0, T_s=THETA_M_CAVITY - 0.02, T_l=THETA_M_CAVITY + 0.02,
                          convective=1)
 
