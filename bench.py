@@ -277,13 +277,15 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark: the readings of the thermal model on "
                          "the paper's Sec. 4.3 problem, one JSON line each")
+    ap.add_argument("--ablation-fo", type=float, default=0.0,
+                    help="with --ablation: one horizon, this Fourier number, all readings")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         return 2
     if args.ablation:
-        return ablation()
+        return ablation(((args.ablation_fo, True),)) if args.ablation_fo > 0 else ablation()
 
     import torch
     from paper_1503_08406_amd import workloads as W
