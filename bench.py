@@ -77,7 +77,7 @@ def active_cell_steps(case, steps, samples, **over):
     return tot, pts[-1][1]
 
 
-def batched(single_mlups, steps=None, trial_steps=16, samples=20):
+def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
     """The batched workload: 512 cavities of seeded uneven sizes and
     parameters (seed 4), advanced together for 10000 steps with the tuned
     launch shape and graph replay of 64 steps; the phase mix for the byte
@@ -87,7 +87,7 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20):
     from paper_1503_08406_amd.dmrt import BatchSolver
     cavs, opts, nsteps = W.cavity_batch()
     steps = steps or nsteps
-    b = BatchSolver(cavs, graph_steps=64, **opts)
+    b = BatchSolver(cavs, graph_steps=64, store_hint=store_hint, **opts)
     rows, blocks, tune_ms = b.tune(trial_steps=trial_steps)
     cells = b.cells
     b.sync()
@@ -104,7 +104,7 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20):
     assert (bad == 0).all(), "non-finite state in the batch"
     b.close()
     # phase accounting replay
-    r = BatchSolver(cavs, graph_steps=64, **opts)
+    r = BatchSolver(cavs, graph_steps=64, store_hint=store_hint, **opts)
     r.set_launch(rows, blocks)
     pts = [(0, int(r.check()[0].sum()))]
     for k in range(1, samples + 1):
@@ -267,6 +267,9 @@ def main():
     ap.add_argument("--T-init", type=float, default=0.0,
                     help="initial temperature (0: solid start as in the workload; "
                          "0.5: liquid start, the flow is solved almost everywhere)")
+    ap.add_argument("--store-hint", type=int, default=0,
+                    help="cache policy of the state stores: 0 by working set, 1 plain, "
+                         "2 write-through, 3 streaming")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-account", action="store_true", help="skip the phase accounting replay")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-cavity measurement")
@@ -293,7 +296,7 @@ def main():
 
     torch.cuda.set_device(0)
     case = W.cavity(nx=args.n, ny=args.n, steps=args.steps, T_init=args.T_init)
-    over = dict(graph_steps=args.graph_steps, block_rows=args.block_rows,
+    over = dict(graph_steps=args.graph_steps, block_rows=args.block_rows, store_hint=args.store_hint,
                 cells_per_lane=args.cells_per_lane)
 
     if args.copy_probe:
@@ -373,7 +376,7 @@ def main():
         "phase": {"active_cells_end": int(act_end), "front_mean_end": round(d["front_mean"], 3)},
     }
     if not args.no_batch:
-        out["batched"] = batched(mlups, steps=args.batch_steps or None)
+        out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
     if not args.no_cpu:

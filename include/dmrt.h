@@ -107,7 +107,11 @@ typedef struct {
                            per-node iteration (R1); 1: source added before streaming
                            (Eq. 30), f_l of all nodes iterated together (R2);
                            default 0                                           */
-    int32_t reserved;   /* 0                                                    */
+    int32_t store_hint; /* cache policy of the step's state stores: 0 by working set
+                           (write-through the L2 when the double-buffered state fits
+                           the 256 MB Infinity Cache, streaming otherwise), 1 plain
+                           write-back, 2 write-through, 3 streaming; the results do
+                           not depend on it; default 0                          */
     double cps_ratio;   /* c_ps / c_pl (sigma_mode 1), 1                        */
     double cm_ratio;    /* (rho c_p)_m / (rho c_pl) of the matrix (sigma_mode 1), 1 */
     double ks_ratio;    /* k_s / k_l (ke_mode 1), 1                             */

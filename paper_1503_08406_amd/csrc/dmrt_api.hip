@@ -141,6 +141,8 @@ int check_opts(const dmrt_opts& o)
     if (o.sigma_mode < 0 || o.sigma_mode > 1 || o.ke_mode < 0 || o.ke_mode > 1 ||
         o.latent_mode < 0 || o.latent_mode > 1)
         return fail(DMRT_EINVAL, "sigma_mode, ke_mode and latent_mode must be 0 or 1");
+    if (o.store_hint < 0 || o.store_hint > 3)
+        return fail(DMRT_EINVAL, "store_hint must be 0, 1, 2 or 3");
     if (!finite_pos(o.cps_ratio) || !finite_pos(o.cm_ratio) || !finite_pos(o.ks_ratio) ||
         !finite_pos(o.km_ratio))
         return fail(DMRT_EINVAL, "cps_ratio, cm_ratio, ks_ratio, km_ratio must be > 0");
@@ -203,6 +205,18 @@ void fill_phys(Phys& P, const dmrt_derived& d, double Ste, const dmrt_opts& o)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Cache policy of the state stores for a state of `bytes` (both buffers):
+// write-through the die's L2 while the state fits the 256 MB Infinity Cache
+// with room to spare (the next step reads it back from there), streaming
+// stores beyond.
+int store_policy(int hint, size_t bytes)
+{
+    if (hint == 1) return dmrtk::ST_PLAIN;
+    if (hint == 2) return dmrtk::ST_WT;
+    if (hint == 3) return dmrtk::ST_NT;
+    return bytes <= (size_t)192 << 20 ? dmrtk::ST_WT : dmrtk::ST_NT;
+}
+
 void set_step_tiling(Geom& G);
 
 // Lattice geometry, boundary description and launch shape of one lattice.
@@ -219,6 +233,7 @@ void fill_geom(Geom& G, int nx, int ny, const dmrt_bc& bc, const dmrt_opts& o)
         G.T_wall[k] = (float)bc.T_wall[k];
     }
     G.block_rows = o.block_rows ? o.block_rows : 4;
+    G.store = store_policy(o.store_hint, (size_t)G.plane * 4 * (2 * dmrtk::FQ + 2 * 5 + 2 + 2 + 3));
     // the thermal-model variants run one node per lane
     const bool variant = o.sigma_mode || o.ke_mode || o.latent_mode;
     G.cells_per_lane = (o.cells_per_lane && !variant) ? o.cells_per_lane : 1;
@@ -544,7 +559,7 @@ void dmrt_opts_default(dmrt_opts* o)
     o->sigma_mode = 0;
     o->ke_mode = 0;
     o->latent_mode = 0;
-    o->reserved = 0;
+    o->store_hint = 0;
     o->cps_ratio = 1.0;
     o->cm_ratio = 1.0;
     o->ks_ratio = 1.0;
@@ -1024,6 +1039,7 @@ struct dmrt_batch {
     int64_t t = 0;
     int check_every = 0, graph_steps = 0;
     int rows = 4, blocks = 0, launch_blocks = 0;
+    int store = 0;  // cache policy of the state stores
     int die[dmrtk::NXCD + 1]{};
     size_t f_len = 0, g_len = 0, fl_len = 0, u_len = 0;  // arena lengths in floats
     char* base = nullptr;
@@ -1124,6 +1140,7 @@ dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p)
     a.flin = b->fl[p];
     a.flout = b->fl[1 - p];
     a.u = b->u;
+    a.store = b->store;
     return a;
 }
 
@@ -1285,6 +1302,7 @@ int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opt
     const size_t bytes_c = align256((size_t)ncav * sizeof(dmrtk::Cavity));
     const size_t bytes_p = align256((size_t)2 * kCountBlocks * ncav * sizeof(long long));
     const size_t total = 2 * (bytes_f + bytes_g + bytes_fl) + bytes_u + bytes_c + bytes_p;
+    b->store = store_policy(o.store_hint, 2 * (bytes_f + bytes_g + bytes_fl) + bytes_u);
     e = hipMalloc(&b->base, total);
     if (e != hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE,

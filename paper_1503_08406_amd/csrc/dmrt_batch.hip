@@ -31,7 +31,7 @@ __device__ __forceinline__ T load_uniform(const T* p)
     return v;
 }
 
-template <int TYB>
+template <int TYB, int SP>
 __global__ __launch_bounds__(TX * TYB) void k_batch_step(BatchArgs a)
 {
     __shared__ FlowStage<TX * TYB> S;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(TX * TYB) void k_batch_step(BatchArgs a)
         B.it_sum = B.it_max = nullptr;
         B.r2f = nullptr;
         B.r2_its = 0;
-        Arrays<BufIO> A(G, B);
+        Arrays<BufIOT<SP>> A(G, B);
         A.eps_u = C.eps;
         A.Ac_u = C.Ac;
         A.Bc_u = C.Bc;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(TX * TYB) void k_batch_step(BatchArgs a)
         const bool narrow = tile.w != 0;
         const int x = tile.y + (narrow ? (lane & 31) : lane);
         const int y = tile.z + (narrow ? 2 * w + (lane >> 5) : w);
-        block_step<BufIO, true, false, true, TX * TYB>(G, P, B, A, x, y, x < G.nx && y < G.ny, S,
+        block_step<BufIOT<SP>, true, false, true, TX * TYB>(G, P, B, A, x, y, x < G.nx && y < G.ny, S,
                                                       parity);
     }
 }
@@ -112,12 +112,25 @@ __global__ __launch_bounds__(256) void k_batch_count(const Cavity* cav, const fl
 
 }  // namespace
 
-hipError_t launch_batch_step(const BatchArgs& a, int rows, int blocks, hipStream_t s)
+namespace {
+template <int SP>
+void launch_batch_sp(const BatchArgs& a, int rows, int blocks, hipStream_t s)
 {
     if (rows == 8)
-        hipLaunchKernelGGL(k_batch_step<8>, dim3(blocks), dim3(TX, 8), 0, s, a);
+        hipLaunchKernelGGL((k_batch_step<8, SP>), dim3(blocks), dim3(TX, 8), 0, s, a);
     else
-        hipLaunchKernelGGL(k_batch_step<4>, dim3(blocks), dim3(TX, 4), 0, s, a);
+        hipLaunchKernelGGL((k_batch_step<4, SP>), dim3(blocks), dim3(TX, 4), 0, s, a);
+}
+}  // namespace
+
+hipError_t launch_batch_step(const BatchArgs& a, int rows, int blocks, hipStream_t s)
+{
+    if (a.store == ST_NT)
+        launch_batch_sp<ST_NT>(a, rows, blocks, s);
+    else if (a.store == ST_WT)
+        launch_batch_sp<ST_WT>(a, rows, blocks, s);
+    else
+        launch_batch_sp<ST_PLAIN>(a, rows, blocks, s);
     return hipGetLastError();
 }
 
@@ -125,8 +138,8 @@ int batch_blocks_per_cu(int rows)
 {
     int nb = 0;
     hipError_t e = rows == 8
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<8>, TX * 8, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<4>, TX * 4, 0);
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<8, ST_PLAIN>, TX * 8, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<4, ST_PLAIN>, TX * 4, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

@@ -87,14 +87,25 @@ inline int tile_blocks(const Geom& G, int TYB)
     return NXCD * ((ntiles + NXCD - 1) / NXCD);
 }
 
-// Access to an array of float planes.  BufIO uses a buffer resource with a
+// Cache policy of the state stores: the cache-policy bits of a gfx950
+// buffer store (sc0 = 1, nt = 2, sc1 = 16).
+//   ST_PLAIN  default write-back through the die's L2;
+//   ST_WT     sc0 | sc1, system scope: written through the L2, for state the
+//             next step reads back from the Infinity Cache (a working set
+//             that fits there);
+//   ST_NT     nt, streaming: for state larger than the Infinity Cache.
+enum : int { ST_PLAIN = 0, ST_WT = 17, ST_NT = 2 };
+
+// Access to an array of float planes.  BufIOT uses a buffer resource with a
 // 32-bit byte offset per node (VGPR) and a 32-bit plane offset (SGPR): one
-// instruction per access, range-checked by the hardware.  PtrIO is the
-// 64-bit pointer form for arrays larger than 4 GB.
-struct BufIO {
+// instruction per access, range-checked by the hardware; SP is the cache
+// policy of its stores.  PtrIO is the 64-bit pointer form for arrays larger
+// than 4 GB.
+template <int SP>
+struct BufIOT {
     using off_t = uint32_t;
     __amdgpu_buffer_rsrc_t r;
-    __device__ __forceinline__ BufIO(const float* p, uint64_t nbytes)
+    __device__ __forceinline__ BufIOT(const float* p, uint64_t nbytes)
         : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(uint32_t)nbytes, 0x00020000))
     {
     }
@@ -109,9 +120,10 @@ struct BufIO {
     __device__ __forceinline__ void st(off_t o, off_t plane_off, float v) const
     {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o,
-                                              __builtin_amdgcn_readfirstlane(plane_off), 0);
+                                              __builtin_amdgcn_readfirstlane(plane_off), SP);
     }
 };
+using BufIO = BufIOT<ST_PLAIN>;
 
 struct PtrIO {
     using off_t = uint64_t;

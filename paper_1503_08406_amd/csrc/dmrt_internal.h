@@ -59,6 +59,7 @@ struct Geom {
     uint32_t st_magic;
     int st_shift;
     int wide;           // 1: 64-bit addressing (arrays beyond a 4 GB window)
+    int store;          // cache policy of the default step's stores (ST_*)
 };
 
 // Device buffers of one step (deviation populations for f).
@@ -121,6 +122,7 @@ struct BatchArgs {
     const float* flin;
     float* flout;
     float* u;
+    int store;  // cache policy of the state stores (ST_*)
 };
 
 // Persistent batched step: `blocks` blocks (a multiple of 8) of 64 x rows

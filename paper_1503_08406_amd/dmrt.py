@@ -41,7 +41,7 @@ class Opts(C.Structure):
                ("graph_steps", C.c_int32), ("block_rows", C.c_int32), ("cells_per_lane", C.c_int32),
                ("stream", C.c_void_p),
                ("sigma_mode", C.c_int32), ("ke_mode", C.c_int32), ("latent_mode", C.c_int32),
-               ("reserved", C.c_int32), ("cps_ratio", C.c_double), ("cm_ratio", C.c_double),
+               ("store_hint", C.c_int32), ("cps_ratio", C.c_double), ("cm_ratio", C.c_double),
                ("ks_ratio", C.c_double), ("km_ratio", C.c_double)]
 
 

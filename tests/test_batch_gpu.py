@@ -61,12 +61,14 @@ def small_reference():
     return out
 
 
-@pytest.mark.parametrize("rows,blocks", [(4, 0), (8, 0), (4, 8), (8, 1024)])
-def test_batch_equals_single_lattices(small_reference, rows, blocks):
+@pytest.mark.parametrize("rows,blocks,hint", [(4, 0, 0), (8, 0, 0), (4, 8, 0), (8, 1024, 0),
+                                              (4, 0, 1), (4, 0, 2), (8, 0, 3)])
+def test_batch_equals_single_lattices(small_reference, rows, blocks, hint):
+    """Any launch shape and any cache policy of the stores (store_hint)."""
     from paper_1503_08406_amd.dmrt import BatchSolver
     cavs, opts = _small_batch()
-    _say("batch", rows, blocks)
-    b = BatchSolver(cavs, **opts)
+    _say("batch", rows, blocks, hint)
+    b = BatchSolver(cavs, store_hint=hint, **opts)
     b.set_launch(rows, blocks)
     b.step(300)
     assert b.time == 300

@@ -333,13 +333,15 @@ def test_cavity_full_length_against_oracle_golden():
 
 def test_launch_shapes_give_identical_results():
     """Every launch shape of the step kernel (block rows x nodes per lane)
-    runs the same per-node arithmetic, so all give the same bits, including
-    a ragged lattice with walls, melting and convection."""
+    and every cache policy of its stores runs the same per-node arithmetic,
+    so all give the same bits, including a ragged lattice with walls,
+    melting and convection."""
     from paper_1503_08406_amd.dmrt import Solver
     case = W.cavity(nx=150, ny=77, Ra=3e5, Da=5e-3, Ste=0.5, T_init=0.2)
     ref = None
-    for rows, cpt in ((4, 1), (4, 2), (8, 1), (8, 2)):
-        s = Solver(case, block_rows=rows, cells_per_lane=cpt)
+    for rows, cpt, hint in ((4, 1, 0), (4, 2, 0), (8, 1, 0), (8, 2, 0), (4, 1, 1), (4, 1, 2),
+                            (4, 1, 3)):
+        s = Solver(case, block_rows=rows, cells_per_lane=cpt, store_hint=hint)
         s.step(700)
         F = s.fields()
         if ref is None:
@@ -347,4 +349,4 @@ def test_launch_shapes_give_identical_results():
             assert (F["fl"] > 0).sum() > 100
         else:
             for k in F:
-                assert np.array_equal(F[k], ref[k]), (rows, cpt, k)
+                assert np.array_equal(F[k], ref[k]), (rows, cpt, hint, k)
