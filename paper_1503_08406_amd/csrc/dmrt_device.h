@@ -125,19 +125,25 @@ struct BufIOT {
 };
 using BufIO = BufIOT<ST_PLAIN>;
 
-struct PtrIO {
+template <int SP>
+struct PtrIOT {
     using off_t = uint64_t;
     char* p;
-    __device__ __forceinline__ PtrIO(const float* q, uint64_t) : p((char*)q) {}
+    __device__ __forceinline__ PtrIOT(const float* q, uint64_t) : p((char*)q) {}
     __device__ __forceinline__ float ld(off_t o, off_t plane_off) const
     {
         return *(const float*)(p + plane_off + o);
     }
     __device__ __forceinline__ void st(off_t o, off_t plane_off, float v) const
     {
-        *(float*)(p + plane_off + o) = v;
+        float* a = (float*)(p + plane_off + o);
+        if constexpr (SP == ST_NT)
+            __builtin_nontemporal_store(v, a);
+        else
+            *a = v;
     }
 };
+using PtrIO = PtrIOT<ST_PLAIN>;
 
 // Velocity closure and D2Q9 MRT collision of one node, on the deviations
 // d_i = f_i - w_i rho0 (rho0 = 1).  Eqs. (24)-(28) give u; the total force

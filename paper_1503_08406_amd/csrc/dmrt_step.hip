@@ -222,11 +222,10 @@ hipError_t launch_r2_io(const Geom& G, const Phys& P, const StepBufs& B, const R
 
 namespace {
 // The default shape (4 rows, one node per lane) with a store cache policy.
-template <int SP>
+template <class IO>
 hipError_t launch_hinted(const Geom& G, const Phys& P, const StepBufs& B, bool flow, bool counted,
                          hipStream_t s)
 {
-    using IO = BufIOT<SP>;
     const dim3 grd(NXCD * G.st_per_xcd), blk(TX, 4);
     if (flow && counted)
         hipLaunchKernelGGL((k_step<IO, true, true, 4, 1, TM_DEFAULT>), grd, blk, 0, s, G, P, B);
@@ -243,10 +242,14 @@ hipError_t launch_hinted(const Geom& G, const Phys& P, const StepBufs& B, bool f
 hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flow, bool counted,
                        hipStream_t s)
 {
-    if (G.wide) return launch_io<PtrIO>(G, P, B, flow, counted, s);
     const bool dflt = G.block_rows == 4 && G.cells_per_lane == 1 && !P.sig_mode && !P.ke_mode;
-    if (dflt && G.store == ST_WT) return launch_hinted<ST_WT>(G, P, B, flow, counted, s);
-    if (dflt && G.store == ST_NT) return launch_hinted<ST_NT>(G, P, B, flow, counted, s);
+    if (G.wide) {
+        // arrays past 4 GB never fit the Infinity Cache: streaming stores
+        if (dflt && G.store == ST_NT) return launch_hinted<PtrIOT<ST_NT>>(G, P, B, flow, counted, s);
+        return launch_io<PtrIO>(G, P, B, flow, counted, s);
+    }
+    if (dflt && G.store == ST_WT) return launch_hinted<BufIOT<ST_WT>>(G, P, B, flow, counted, s);
+    if (dflt && G.store == ST_NT) return launch_hinted<BufIOT<ST_NT>>(G, P, B, flow, counted, s);
     return launch_io<BufIO>(G, P, B, flow, counted, s);
 }
 
