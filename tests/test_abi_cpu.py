@@ -47,7 +47,8 @@ def _args(**over):
 
 
 @pytest.mark.parametrize("what", ["grid", "periodic_pair", "kind", "tau", "TlTs", "rate",
-                                  "graph_odd", "Ste", "noeps", "varpi"])
+                                  "graph_odd", "Ste", "noeps", "varpi", "sigma_mode", "ratio",
+                                  "store_hint", "cps_enthalpy"])
 def test_create_rejects_bad_arguments_without_device(what):
     from paper_1503_08406_amd import dmrt
     lib = dmrt.lib()
@@ -73,6 +74,15 @@ def test_create_rejects_bad_arguments_without_device(what):
         Ste = 0.0
     elif what == "varpi":
         o.varpi = -5.0
+    elif what == "sigma_mode":
+        o.sigma_mode = 2
+    elif what == "ratio":
+        o.ke_mode, o.km_ratio = 1, 0.0
+    elif what == "store_hint":
+        o.store_hint = 4
+    elif what == "cps_enthalpy":
+        # Eq. (41) needs En_l = T_l + 1/St above En_s = c_ps T_s
+        o.sigma_mode, o.cps_ratio, o.T_s, o.T_l = 1, 10.0, 0.5, 0.6
     h = C.c_void_p()
     ep = None if what == "noeps" else eps.ctypes.data_as(C.c_void_p)
     rc = lib.dmrt_create(C.byref(g), ep, None, None, Ra, Da, Pr, Ste, C.byref(bc), C.byref(o),
@@ -119,7 +129,7 @@ def test_opts_defaults_are_the_papers():
         (-2.0, 1.1, 1.1, 1.2, 1.5, 1.5, 0.1, 1.0, 175.0)
 
 
-@pytest.mark.parametrize("what", ["empty", "eps", "eps_zero", "bc", "Pr", "rows"])
+@pytest.mark.parametrize("what", ["empty", "eps", "eps_zero", "bc", "Pr", "rows", "variant"])
 def test_batch_create_rejects_bad_arguments_without_device(what):
     """Batch creation validates every cavity before touching the device and
     names the first bad one."""
@@ -144,6 +154,8 @@ def test_batch_create_rejects_bad_arguments_without_device(what):
         cav[2].Pr = -1.0
     elif what == "rows":
         o.block_rows = 6
+    elif what == "variant":
+        o.latent_mode = 1
     h = C.c_void_p()
     rc = lib.dmrt_batch_create(n, cav, C.byref(o), C.byref(h))
     assert rc == dmrt.DMRT_EINVAL and not h.value
