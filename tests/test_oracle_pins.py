@@ -167,6 +167,31 @@ def test_mrt_with_equal_rates_is_porous_bgk(oracle_mod):
         np.testing.assert_allclose(got, ref, atol=1e-15)
 
 
+def test_mrt_step_equals_dense_velocity_space_form(oracle_mod):
+    """Eq. (13) in velocity space with distinct rates: f+ = f - M^-1 Lambda
+    (M f - M f^eq) + M^-1 (I - Lambda/2) M F_i, assembled from textbook parts
+    only (M from the Lallemand-Luo polynomials, the porous equilibrium and
+    the Guo-Zhao porous forcing in velocity space, M^-1 by a dense solve),
+    equals the oracle's moment-space step (Eq. 20)."""
+    L = oracle_mod.lattice()
+    M, _, _ = _M_indep(oracle_mod)
+    Minv = np.linalg.inv(M)
+    e, w = L["e9"].astype(float), L["w9"]
+    for _ in range(60):
+        s = np.concatenate([[1.0], RNG.uniform(0.6, 1.9, 8)])
+        f = w * (1 + 0.05 * RNG.standard_normal(9))
+        rho = f.sum()
+        ux, uy, Fx, Fy = 0.03 * RNG.standard_normal(4)
+        phi = RNG.uniform(0.1, 1.0)
+        eu = e @ np.array([ux, uy])
+        feq = w * (rho + (eu / CS2 + eu ** 2 / (2 * CS2 ** 2 * phi) - (ux * ux + uy * uy) / (2 * CS2 * phi)))
+        Lam = np.diag(s)
+        ref = f - Minv @ Lam @ (M @ f - M @ feq) + Minv @ (np.eye(9) - Lam / 2) @ M @ \
+            _guo_forcing(e, w, ux, uy, Fx, Fy, phi)
+        got = oracle_mod.collide_f(f, rho, ux, uy, Fx, Fy, phi, s)
+        np.testing.assert_allclose(got, ref, atol=2e-15)
+
+
 def test_conserved_moment_rates_do_not_matter(oracle_mod):
     """Eq. (20) with Eq. (17): the post-collision momentum is rho0 u + F/2 for
     any s_3 = s_5, because m_3 = rho0 u_x - F_x/2 by Eq. (25)."""
