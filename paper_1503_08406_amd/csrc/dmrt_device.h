@@ -52,22 +52,19 @@ __device__ __forceinline__ bool tile_origin(const Geom& G, int& x0, int& y0)
 // Tile origin of the step kernel from the host-computed tiling constants:
 // q = tile / st_tx via q = (hi + ((t - hi) >> 1)) >> (shift - 1), hi =
 // mulhi(t, magic) (division by an invariant integer, Granlund & Montgomery).
+// Branch-free, so that nothing stands between the kernel-argument loads and
+// the first memory batch.
 template <int ROWS>
 __device__ __forceinline__ bool step_tile_origin(const Geom& G, int& x0, int& y0)
 {
     const uint32_t b = blockIdx.x;
     const uint32_t tile = (b & (NXCD - 1)) * (uint32_t)G.st_per_xcd + (b >> 3);
-    if (tile >= (uint32_t)G.st_ntiles) return false;
-    uint32_t q;
-    if (G.st_shift == 0) {
-        q = tile;  // one tile per row
-    } else {
-        const uint32_t hi = __umulhi(tile, G.st_magic);
-        q = (hi + ((tile - hi) >> 1)) >> (G.st_shift - 1);
-    }
+    const uint32_t hi = __umulhi(tile, G.st_magic);
+    const uint32_t qd = (hi + ((tile - hi) >> 1)) >> ((uint32_t)(G.st_shift - 1) & 31u);
+    const uint32_t q = G.st_shift == 0 ? tile : qd;  // shift 0: one tile per row
     x0 = (int)(tile - q * (uint32_t)G.st_tx) * TX;
     y0 = (int)q * ROWS;
-    return true;
+    return tile < (uint32_t)G.st_ntiles;
 }
 
 // Keeps a batch of loads together: the empty statement takes every value as

@@ -31,18 +31,22 @@ template <class IO, bool FLOW, bool COUNT, int TYB, int CPT, int TM>
 __global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
 {
     // a tile of 64 x (TYB * CPT) nodes
-    int x0, y0;
-    if (!step_tile_origin<TYB * CPT>(G, x0, y0)) return;
+    int x0 = 0, y0 = 0;
+    const bool tile = step_tile_origin<TYB * CPT>(G, x0, y0);
     const Arrays<IO> A(G, B);
     const int x = x0 + (int)threadIdx.x;
     if (CPT == 1) {
-        // one node per lane, flow work gathered onto the lowest lanes
+        // one node per lane, flow work gathered onto the lowest lanes.  A
+        // block past the last tile runs with no valid lane rather than
+        // returning early: with no branch before it, the compiler issues all
+        // kernel-argument loads at once instead of in dependent rounds.
         __shared__ FlowStage<TX * TYB> S;
         const int y = y0 + (int)threadIdx.y;
-        block_step<IO, FLOW, COUNT, false, TX * TYB, TM>(G, P, B, A, x, y, x < G.nx && y < G.ny, S,
-                                                         0);
+        block_step<IO, FLOW, COUNT, false, TX * TYB, TM>(G, P, B, A, x, y,
+                                                         tile && x < G.nx && y < G.ny, S, 0);
         return;
     }
+    if (!tile) return;
     // CPT nodes per lane, TYB rows apart: the first load batch of all of
     // them is issued before any is finished
     Node<IO> n[CPT];
