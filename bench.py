@@ -369,7 +369,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": traffic,
-                     "kernel": "k_step<BufIO, flow>", "kernel_ms": round(kern_ms, 6),
+                     "kernel": "k_step (flow, 4 rows, 1 node per lane)", "kernel_ms": round(kern_ms, 6),
                      "bytes_per_launch": round(bytes_per_launch),
                      "fluid_fraction_mean": round(fluid_frac, 5),
                      "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID}},
