@@ -216,3 +216,21 @@ def test_r2_graph_replay_and_iteration_counts():
     mx, mean = a.step_counted(5)
     _say("r2 sweeps per step: max %d mean %.2f" % (mx, mean))
     assert 1 <= mean <= mx <= 200
+
+
+@pytest.mark.parametrize("var", ["default", "sigma_ke", "r2"])
+def test_counted_steps_equal_plain_steps(var):
+    """The counted step (per-node enthalpy-iteration statistics) is a separate
+    instantiation of the step kernels; it must advance the state bit for bit
+    like the plain one, for the default model, the variants and R2."""
+    from paper_1503_08406_amd.dmrt import Solver
+    case = W.cavity(nx=96, ny=80, steps=300, Ra=1e5, Da=5e-3, Ste=0.5, seed=3, T_init=0.39)
+    over = {"default": {}, "sigma_ke": VARIANTS["both"], "r2": dict(latent_mode=1)}[var]
+    a = Solver(case, **over)
+    b = Solver(case, **over)
+    a.step(120)
+    mx, mean = b.step_counted(120)
+    Fa, Fb = a.fields(), b.fields()
+    for k in Fa:
+        assert np.array_equal(Fa[k], Fb[k]), (var, k)
+    assert (Fa["fl"] > 0).sum() > 100 and 1 <= mean <= mx
