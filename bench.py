@@ -284,7 +284,7 @@ def main():
                     help="with --ablation: one horizon, this Fourier number, all readings")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported"
+        print("bench.py: runs on one GPU only; --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         return 2
     if args.ablation:

@@ -1,6 +1,6 @@
 """Helpers shared by the GPU parity tests: build the HIP solver and the FP64
 oracle on the same workload and compare them with the tolerances of the
-spec contract (T: relative L-inf 1e-4; u: relative L-inf 1e-3;
+parity contract (T: relative L-inf 1e-4; u: relative L-inf 1e-3;
 f_l: L-inf 1e-3; front: 0.5 lattice units)."""
 import numpy as np
 

@@ -1,5 +1,5 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
-the same seeded inputs.  Tolerances are the spec contract (T relative
+the same seeded inputs.  Tolerances are the parity contract (T relative
 L-inf <= 1e-4, u relative L-inf <= 1e-3, f_l L-inf <= 1e-3, front within 0.5
 lattice units); single steps on random states are checked population by
 population at FP32 round-off level."""
