@@ -428,8 +428,17 @@ __device__ __forceinline__ void block_step(const Geom& G, const Phys& P, const S
     const int tid = w * 64 + lane;
     Node<IO> n;
     float T1 = 0.0f, fl1 = 0.0f, isig1 = 0.0f, ux = 0.0f, uy = 0.0f;
+    // issue the first load batch at raised wave priority, so that waves
+    // still computing do not delay the memory requests of new ones.  The
+    // priority belongs to the wavefront; it is lowered right after the loads
+    // inside the lane condition (placed outside, the compiler also lowers it
+    // on the masked-off path before the loads).  A wavefront with no valid
+    // lane (past the last tile) keeps the raised priority; it only meets the
+    // block's barriers.
+    __builtin_amdgcn_s_setprio(2);
     if (valid) {
         node_load<IO, FLOW, USTAT>(G, A, x, y, n);
+        __builtin_amdgcn_s_setprio(0);
         node_enthalpy<IO, FLOW, COUNT, TM>(G, P, B, A, n, T1, fl1, isig1);
     }
     if (FLOW) {
