@@ -164,7 +164,9 @@ int dmrt_create(const dmrt_grid *grid, const float *eps, const float *K, const f
                 const dmrt_opts *opts, dmrt_t **out);
 
 /* Advance n >= 0 time steps (enqueued; returns before they finish unless a
- * NaN check runs).  DMRT_ENONFINITE names the step in dmrt_last_error(). */
+ * NaN check runs).  DMRT_ENONFINITE names the step in dmrt_last_error().
+ * One step is one kernel launch; with latent_mode 1 it is 2 + fl_maxit
+ * launches (the global iteration; sweeps after convergence return at once). */
 int dmrt_step(dmrt_t *h, int64_t n);
 
 /* Fields at the current time: T (Eq. 33), u (Eq. 26; 0 in solid cells) and
