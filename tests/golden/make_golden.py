@@ -13,8 +13,11 @@ nothing here comes from the HIP path.
   batch_512_smallest.npz the three smallest cavities of the 512-cavity batch
                          (seed 4), each over the batch's 10000 steps: T, u,
                          f_l in full.
+  gallium_200.npz        the Sec. 4.3 problem as the paper sets it up (200x200,
+                         gallium in glass beads): T, u, f_l in full at Fourier
+                         numbers 0.457 and 1.829 (209368 and 837931 steps).
 
-Usage: python tests/golden/make_golden.py [corner|cavity|cavity_long|batch ...]
+Usage: python tests/golden/make_golden.py [corner|cavity|cavity_long|batch|gallium ...]
 """
 import os
 import sys
@@ -125,6 +128,25 @@ def batch():
         for n in ("T", "ux", "uy", "fl"):
             out["%s_%d" % (n, k)] = F[n]
     np.savez_compressed(os.path.join(HERE, "batch_512_smallest.npz"), **out)
+
+
+GALLIUM_FO = (0.457, 1.829)
+
+
+def gallium():
+    case = W.gallium_cavity()
+    o = make_oracle(case, threads=int(os.environ.get("ORACLE_THREADS", "0")) or None)
+    steps = [W.gallium_fourier_steps(case, fo) for fo in GALLIUM_FO]
+    out = dict(fo=np.array(GALLIUM_FO), steps=np.array(steps))
+    t = time.time()
+    for k, n in enumerate(steps):
+        o.step(n - o.time)
+        F = o.fields()
+        for q in ("T", "ux", "uy", "fl"):
+            out["%s_%d" % (q, k)] = F[q].astype(np.float32)
+        out["front_%d" % k] = front_rows(F["fl"])
+        print("gallium: step %d (%.0f s)" % (n, time.time() - t), flush=True)
+        np.savez_compressed(os.path.join(HERE, "gallium_200.npz"), **out)
 
 
 if __name__ == "__main__":
