@@ -105,8 +105,8 @@ typedef struct {
                            k_m = km_ratio (lambda, alpha_ratio unused); default 0 */
     int32_t latent_mode;/* 0: latent source after streaming at the receiving node,
                            per-node iteration (R1); 1: source added before streaming
-                           (Eq. 30), f_l of all nodes iterated together (R2);
-                           default 0                                           */
+                           (Eq. 30), f_l of all nodes iterated together (R2), one
+                           launch per sweep, so fl_maxit <= 4096; default 0      */
     int32_t store_hint; /* cache policy of the step's state stores: 0 by working set
                            (write-through the L2 when the double-buffered state fits
                            the 256 MB Infinity Cache, streaming otherwise), 1 plain

@@ -590,6 +590,8 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     if ((rc = check_opts(o)) || (rc = check_bc(bc))) return rc;
     if (o.sigma_mode && !(o.T_l + 1.0 / Ste > o.cps_ratio * o.T_s))
         return fail(DMRT_EINVAL, "sigma_mode 1 needs T_l + 1/St > cps_ratio T_s");
+    if (o.latent_mode && o.fl_maxit > 4096)
+        return fail(DMRT_EINVAL, "latent_mode 1 launches fl_maxit sweeps per step: fl_maxit <= 4096");
     const long long nx = grid->nx, ny = grid->ny;
     const long long pitch = (nx + 63) / 64 * 64;
     if (ny * pitch >= (1ll << 31)) return fail(DMRT_EINVAL, "lattice too large (%lld x %lld)", nx, ny);
