@@ -54,7 +54,12 @@ def cpu_baseline(case, budget_s=15.0):
     o.step(n)
     el = time.perf_counter() - t
     cells = case["nx"] * case["ny"]
+    o1 = oracle_from_case(case, nthreads=1)  # one thread, a short sample
+    t = time.perf_counter()
+    o1.step(3)
+    el1 = time.perf_counter() - t
     return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "value_1_thread": round(cells * 3 / el1 / 1e6, 3),
             "kind": "oracle",
             "sample": "steps 5..%d of the %dx%d cavity from its initial state (FP64 oracle, "
                       "%d OpenMP threads, %.1f s)" % (5 + n, case["nx"], case["ny"], cores, el)}
@@ -75,6 +80,42 @@ def active_cell_steps(case, steps, samples, **over):
         tot += 0.5 * (a0 + a1) * (t1 - t0)
     s.close()
     return tot, pts[-1][1]
+
+
+def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
+    """The cavity workload at n x n (4096^2: 2.5 GB of state, past the
+    Infinity Cache, so the step streams from HBM), timed like the main run;
+    roofline with the same phase-mixed byte model."""
+    import torch
+    from paper_1503_08406_amd import workloads as W
+    from paper_1503_08406_amd.dmrt import Solver
+    case = W.cavity(nx=n, ny=n, steps=steps)
+    s = Solver(case, graph_steps=graph_steps)
+    s.step(warmup)
+    s.sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(s.stream)
+    s.step(steps)
+    ev1.record(s.stream)
+    s.sync()
+    wall = time.perf_counter() - t0
+    kern_ms = ev0.elapsed_time(ev1) / steps
+    d = s.diag()
+    s.close()
+    act_steps, _ = active_cell_steps(case, warmup + steps, 20, graph_steps=graph_steps)
+    cells = n * n
+    ff = act_steps / (cells * (warmup + steps))
+    bpl = (BYTES_FLUID * ff + BYTES_SOLID * (1 - ff)) * cells
+    return {"workload": "the same cavity at %dx%d (%.2f GB of state), steps %d..%d"
+                        % (n, n, cells * 148 / 1e9, warmup, warmup + steps),
+            "value": round(cells * steps / wall / 1e6, 2), "unit": "MLUPS",
+            "kernel_ms": round(kern_ms, 6),
+            "roofline": {"bound": "hbm", "achieved": round(bpl / (kern_ms * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": round(bpl / (kern_ms * 1e-3) / HBM_PEAK, 4),
+                         "fluid_fraction_mean": round(ff, 5)},
+            "nonfinite": int(d["nonfinite"])}
 
 
 def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
@@ -275,6 +316,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-cavity measurement")
     ap.add_argument("--batch-steps", type=int, default=0, help="batched steps (0: the workload's)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-hbm", action="store_true",
+                    help="skip the 4096^2 point (state beyond the Infinity Cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--ablation", action="store_true",
@@ -369,6 +412,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": traffic,
+                     "traffic_GBps": None if traffic is None else round(traffic / (kern_ms * 1e-3) / 1e9, 1),
                      "kernel": "k_step (flow, 4 rows, 1 node per lane)", "kernel_ms": round(kern_ms, 6),
                      "bytes_per_launch": round(bytes_per_launch),
                      "fluid_fraction_mean": round(fluid_frac, 5),
@@ -379,6 +423,8 @@ def main():
         out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
+    if not args.no_hbm:
+        out["hbm_point"] = hbm_point()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
