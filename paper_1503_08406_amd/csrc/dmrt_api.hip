@@ -331,20 +331,24 @@ int build_graph(dmrt* h, int p)
         hipError_t e = enqueue_step(h, false);
         h->cur = 1 - h->cur;
         if (e != hipSuccess) {
-            hipGraph_t gdrop;
+            hipGraph_t gdrop = nullptr;
             (void)hipStreamEndCapture(h->stream, &gdrop);
             if (gdrop) (void)hipGraphDestroy(gdrop);
             h->cur = save;
             return fail(DMRT_EDEVICE, "launch during capture: %s", hipGetErrorString(e));
         }
     }
-    hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamEndCapture(h->stream, &graph));
-    hipError_t e = hipGraphInstantiate(&h->graph[p], graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
     h->cur = save;
     h->t = tsave;
-    if (e != hipSuccess) return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (e != hipSuccess) return fail(DMRT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->graph[p], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->graph[p] = nullptr;
+        return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
     return DMRT_OK;
 }
 
@@ -510,6 +514,19 @@ int enqueue_adjoint(dmrt* h)
         }
     }
     return DMRT_OK;
+}
+
+// The replay graphs hold the launches of one flow mode (flow kernels or the
+// conduction-only ones): drop them when the mode changes.
+void set_flow(dmrt* h, bool flow)
+{
+    if (flow == h->flow) return;
+    h->flow = flow;
+    for (auto& g : h->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
 }
 
 int check_finite(dmrt* h)
@@ -692,7 +709,7 @@ int dmrt_set_state(dmrt_t* h, const float* f, const float* g, const float* fl)
         if (g) { dg = s; s += 5 * ncell; HIPCHK(hipMemcpyAsync(dg, g, 5 * ncell * 4, hipMemcpyDefault, h->stream)); }
         if (fl) { dfl = s; HIPCHK(hipMemcpyAsync(dfl, fl, ncell * 4, hipMemcpyDefault, h->stream)); }
     }
-    if (f) h->flow = true;  // a given velocity field may move without gravity
+    if (f) set_flow(h, true);  // a given velocity field may move without gravity
     const int a = h->cur;
     HIPCHK(dmrtk::launch_load_state(G, h->P, df, dg, dfl, h->f[a], h->g[a], h->fl[a], h->ux, h->uy,
                                    h->eps, h->Ac, h->Bc, h->flow, h->stream));
@@ -864,7 +881,7 @@ int dmrt_load(dmrt_t* h, const void* buf, size_t n)
     HIPCHK(hipMemcpyAsync(h->uy, p + (fq + 7) * pb, pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->t = (int64_t)hdr[4];
-    h->flow = h->flow || hdr[5] != 0;
+    if (hdr[5] != 0) set_flow(h, true);
     return DMRT_OK;
 }
 

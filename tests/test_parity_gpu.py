@@ -219,6 +219,34 @@ def test_graph_replay_equals_plain_launches():
     assert np.array_equal(s1.fields()["T"], s2.fields()["T"])
 
 
+def test_graph_replay_follows_a_switch_to_flow(L):
+    """A conduction-only lattice (Ra = 0) that is handed a velocity field,
+    by dmrt_set_state or by loading a checkpoint of a moving state, runs the
+    flow kernels from then on, also from graphs captured before the switch."""
+    from paper_1503_08406_amd.dmrt import Solver
+    nx, ny = 70, 37
+    case = _random_case(nx, ny, "box", Ra=0.0)
+    f, g, fl = W.random_state(nx, ny, 11, L["w9"], L["w5"])
+    s1 = Solver(case)
+    s2 = Solver(case, graph_steps=4)
+    s3 = Solver(case, graph_steps=4)
+    for s in (s1, s2, s3):
+        s.step(8)  # s2 and s3 capture their conduction-only graphs here
+    _say("switch to flow by set_state")
+    s1.set_state(f, g, fl)
+    s2.set_state(f, g, fl)
+    _say("switch to flow by load")
+    s3.load(s1.save())
+    for s in (s1, s2, s3):
+        s.step(8)
+    a = s1.fields()
+    assert np.abs(a["ux"]).max() > 1e-5
+    for s in (s2, s3):
+        b = s.fields()
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+
+
 def test_nonfinite_state_is_reported(L):
     """A NaN planted in the state (from the host) makes dmrt_step return
     DMRT_ENONFINITE when checking is on."""
