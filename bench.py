@@ -82,6 +82,38 @@ def active_cell_steps(case, steps, samples, **over):
     return tot, pts[-1][1]
 
 
+def plain_copy(nbytes, copies=64, reps=10):
+    """What a plain device copy reaches for the same bytes: copies back and
+    forth between two buffers of nbytes/2 each (each copy reads half and
+    writes half), replayed from a graph and timed with HIP events.  This is
+    the rate a pure stream of this traffic and working-set size attains on
+    the device, next to the nominal HBM peak."""
+    import torch
+    n = max(1, int(nbytes) // 8)  # floats per buffer
+    a = torch.ones(n, device="cuda")
+    b = torch.zeros(n, device="cuda")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(4):
+            b.copy_(a)
+            a.copy_(b)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            for _ in range(copies // 2):
+                b.copy_(a)
+                a.copy_(b)
+        g.replay()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            g.replay()
+        e1.record(st)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / (reps * copies)
+    del g, a, b
+    return {"bytes": 8 * n, "us": round(us, 3), "GBps": round(8 * n / (us * 1e-6) / 1e9, 1)}
+
+
 def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
     """The cavity workload at n x n (4096^2: 2.5 GB of state, past the
     Infinity Cache, so the step streams from HBM), timed like the main run;
@@ -107,6 +139,8 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
     cells = n * n
     ff = act_steps / (cells * (warmup + steps))
     bpl = (BYTES_FLUID * ff + BYTES_SOLID * (1 - ff)) * cells
+    cp = plain_copy(bpl)
+    cp["frac_of_copy"] = round(cp["us"] / (kern_ms * 1e3), 3)
     return {"workload": "the same cavity at %dx%d (%.2f GB of state), steps %d..%d"
                         % (n, n, cells * 148 / 1e9, warmup, warmup + steps),
             "value": round(cells * steps / wall / 1e6, 2), "unit": "MLUPS",
@@ -114,7 +148,7 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
             "roofline": {"bound": "hbm", "achieved": round(bpl / (kern_ms * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                          "frac": round(bpl / (kern_ms * 1e-3) / HBM_PEAK, 4),
-                         "fluid_fraction_mean": round(ff, 5)},
+                         "fluid_fraction_mean": round(ff, 5), "plain_copy": cp},
             "nonfinite": int(d["nonfinite"])}
 
 
@@ -389,6 +423,9 @@ def main():
             traffic = round((tr["bytes_per_cell_solid"] * (1 - fluid_frac) +
                              tr["bytes_per_cell_fluid"] * fluid_frac) * cells)
 
+    cp = plain_copy(traffic or bytes_per_launch)
+    cp["frac_of_copy"] = round(cp["us"] / (kern_ms * 1e3), 3)
+
     out = {
         "metric": "MLUPS (flow+thermal)",
         "value": round(mlups, 2),
@@ -416,7 +453,8 @@ def main():
                      "kernel": "k_step (flow, 4 rows, 1 node per lane)", "kernel_ms": round(kern_ms, 6),
                      "bytes_per_launch": round(bytes_per_launch),
                      "fluid_fraction_mean": round(fluid_frac, 5),
-                     "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID}},
+                     "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID},
+                     "plain_copy": cp},
         "phase": {"active_cells_end": int(act_end), "front_mean_end": round(d["front_mean"], 3)},
     }
     if not args.no_batch:
