@@ -352,6 +352,42 @@ def test_brinkman_channel_profile(oracle_mod, Da, tol):
     assert np.abs(F["ux"]).max() < 1e-14
 
 
+def test_channel_bounded_by_solid_nodes(oracle_mod):
+    """The solid sources of the link-wise extrapolation (Eq. 29 applied at
+    nodes with f_l = 0, Sec. 4): a channel whose no-slip walls are two columns
+    of solid phase-change material inside the lattice, not ghost walls, gives
+    the Poiseuille parabola with the walls at the solid node centres.  The
+    solid columns are held below T_s by cold outer walls; a tiny Stefan number
+    keeps the liquid next to them liquid, and a reference temperature far
+    below the field makes the buoyancy force uniform to 5e-5."""
+    nx, phi, T0 = 34, 0.6, -1000.0
+    c = W.make_case("solid_ch", nx, 1, [1, 1, 0, 0], [0.5, 0.5, 0, 0], Ra=0.1, Da=1e6, Pr=1,
+                    Ste=1e-6, eps=phi, Feps=0.0, H=32, T_init=1.02, T_s=0.98, T_l=1.02,
+                    convective=1, Ma=1e-3, T0=T0)
+    o = oracle_from_case(c)
+    d = o.derived
+    L = oracle_mod.lattice()
+    fl = np.ones((1, nx))
+    fl[0, [0, -1]] = 0.0
+    T = np.full((1, nx), 1.02)
+    T[0, [0, -1]] = 0.76
+    f = np.asarray(L["w9"])[:, None, None] * np.ones((9, 1, nx))
+    g = np.asarray(L["w5"])[:, None, None] * T[None]
+    o.set_state(f, g, fl)
+    o.step(60000)
+    F = o.fields()
+    assert F["fl"][0, 0] == 0 and F["fl"][0, -1] == 0, "the solid columns melted"
+    assert F["fl"][0, 1:-1].min() > 0.99
+    G = d["gbeta"] * (F["T"][0] - T0)
+    assert np.ptp(G[1:-1]) / G[1:-1].mean() < 1e-4
+    x = np.arange(nx)
+    ua = phi * G[1:-1].mean() / (2 * d["nu_e"]) * x * (nx - 1 - x)
+    uy = F["uy"][0]
+    assert uy[0] == 0 and uy[-1] == 0
+    assert np.abs(uy - ua).max() / ua.max() < 4e-3
+    assert np.abs(F["ux"]).max() < 1e-12
+
+
 def test_shear_wave_decay_viscosity_and_darcy(oracle_mod):
     """Eq. (2) linearised in a periodic box: a shear wave u_x = U sin(q y)
     decays at nu_e q^2 + phi nu_l / K, with nu_e = c_s^2 (tau_nu - 1/2)
