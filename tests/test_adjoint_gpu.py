@@ -177,7 +177,7 @@ def test_adjoint_full_size_inverse_problem():
     for _ in range(3):  # within 3 nodes of the final liquid region
         near = near | np.roll(near, 1, 0) | np.roll(near, -1, 0) | np.roll(near, 1, 1) | np.roll(near, -1, 1)
     gn = g.cpu().numpy()
-    _say("inverse problem: L %.6e, liquid %d, |g| %.3e" % (float(L), int(liquid.sum()),
+    _say("inverse problem: L %.6e, liquid %d, |g| %.3e" % (float(L.detach()), int(liquid.sum()),
                                                            float(g.norm())))
     assert liquid.sum() > 0 and np.all(gn[~near] == 0.0) and np.abs(gn[liquid]).max() > 0
     # v = g / |g| is spread over the melted strip, so a step h changes no

@@ -200,6 +200,42 @@ def test_save_load_resume_is_bit_identical():
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_channel_bounded_by_solid_nodes(L):
+    """A channel whose no-slip walls are two columns of solid nodes inside the
+    lattice (extrapolation at solid sources, Eq. 29), run to steady state:
+    GPU against the oracle, and both against the Poiseuille parabola with the
+    walls at the solid node centres.  T is compared in absolute terms at
+    2e-3: the tiny Stefan number multiplies the FP32 rounding of f_l (and the
+    stopping tolerance of the enthalpy iteration, set below FP32 resolution
+    here) by phi/(sigma St) = 6000 in the latent correction of the two mushy
+    columns, whose temperature sets the whole liquid's."""
+    nx, phi, T0 = 34, 0.6, -1000.0
+    case = W.make_case("solid_ch", nx, 1, [1, 1, 0, 0], [0.9, 0.9, 0, 0], Ra=0.1, Da=1e6, Pr=1,
+                       Ste=1e-4, eps=phi, Feps=0.0, H=32, T_init=1.02, T_s=0.98, T_l=1.02,
+                       convective=1, Ma=1e-3, T0=T0)
+    fl = np.ones((1, nx), np.float32)
+    fl[0, [0, -1]] = 0.0
+    T = np.full((1, nx), 1.02)
+    T[0, [0, -1]] = 0.96
+    f = (np.asarray(L["w9"])[:, None, None] * np.ones((9, 1, nx))).astype(np.float32)
+    g = (np.asarray(L["w5"])[:, None, None] * T[None]).astype(np.float32)
+    s, o = pair(case, gpu_over=dict(fl_tol=1e-9))
+    s.set_state(f, g, fl)
+    o.set_state(f.astype(float), g.astype(float), fl.astype(float))
+    _say("solid-bounded channel 60000 steps")
+    s.step(60000)
+    o.step(60000)
+    Fg, Fo = s.fields(), o.fields()
+    assert Fg["fl"][0, 0] == 0 and Fg["fl"][0, -1] == 0
+    assert np.abs(Fg["fl"] - Fo["fl"]).max() < 1e-3
+    assert np.abs(Fg["uy"] - Fo["uy"]).max() / np.abs(Fo["uy"]).max() < 1e-3
+    assert np.abs(Fg["T"] - Fo["T"]).max() < 2e-3
+    d = o.derived
+    x = np.arange(nx)
+    ua = phi * d["gbeta"] * (Fo["T"][0, 2:-2].mean() - T0) / (2 * d["nu_e"]) * x * (nx - 1 - x)
+    assert np.abs(Fg["uy"][0] - ua).max() / ua.max() < 4e-3
+
+
 def test_graph_replay_equals_plain_launches():
     """Steps replayed from a captured HIP graph give the same bits as plain
     launches, across several replays with eager work in between."""
