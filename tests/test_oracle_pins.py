@@ -742,3 +742,43 @@ def test_melting_node_joins_at_the_local_density(oracle_mod):
     np.testing.assert_allclose(fs, np.broadcast_to(w9[:, None, None] * rho, fs.shape), atol=1e-15)
     F = o.fields()
     assert np.abs(F["ux"]).max() < 1e-16 and np.abs(F["uy"]).max() < 1e-16
+
+
+def test_domain_of_dependence_is_one_node_per_step():
+    """Every part of a step reaches one node at most: pulls from the nearest
+    neighbours (Eqs. 21, 36), a node-local closure, collision and enthalpy
+    update, extrapolations from the node's own values (Eq. 29), and a restart
+    of a melted node from its nearest neighbours.  So after N steps a node
+    depends only on the state within N lattice units, and two different
+    windows of a melting, convecting cavity agree bit for bit on the nodes
+    farther than N from their inner sides, although those sides are walls at
+    a temperature that melts the cavity there (a disturbance that leaves them
+    at once).  Nearer to those sides the windows differ, up to about 0.8 N
+    from them (the leading edge of a disturbance that travels one node per
+    step is below FP64 resolution for its last ~20 nodes).  The GPU test of
+    the 4096^2 cavity relies on this."""
+    n, N = 512, 96
+    case = W.cavity(nx=n, ny=n, steps=N, Ra=1e5, Da=1e-2)
+
+    def window(wx, wy, y0):
+        win = W.make_case("window", wx, wy, [1, 1, 1, 1], [1.0, 0.5, 0.5, 0.5], Ra=case["Ra"],
+                          Da=case["Da"], Pr=case["Pr"], Ste=case["Ste"],
+                          eps=case["eps"][y0:y0 + wy, :wx], K=case["K"][y0:y0 + wy, :wx],
+                          H=float(n), **case["opts"])
+        o = oracle_from_case(win)
+        o.step(N)
+        return o.fields()
+
+    wx, wy, y0 = N + 40, 2 * N + 40, 150
+    A = window(wx, wy, y0)
+    B = window(wx + 17, wy + 30, y0 - 13)
+    ex, ey = slice(0, wx - N), slice(N, wy - N)
+    for k in ("T", "ux", "uy", "fl"):
+        assert np.array_equal(A[k][ey, ex], B[k][13:13 + wy][ey, ex]), k
+    assert (A["fl"][ey, ex] > 0).sum() >= 40 and np.abs(A["uy"][ey, ex]).max() > 1e-6
+    # the inner walls are felt up to ~0.8 N away: in y below the exact rows,
+    # in x beside the exact columns
+    d = A["T"] != B["T"][13:13 + wy, :wx]
+    rows = np.where(d[:, ex].any(1))[0]
+    cols = np.where(d[ey].any(0))[0]
+    assert rows[rows < N].max() >= 0.7 * N and cols.min() <= wx - 0.7 * N

@@ -358,6 +358,42 @@ def test_cavity_full_size_against_oracle_golden():
     assert np.all(F["fl"][:, k:] == 0)  # nothing melted beyond the strip
 
 
+def test_cavity_4096_window_against_oracle():
+    """The 4096x4096 cavity in the configuration the benchmark times for its
+    state beyond the Infinity Cache (graph replay of 64 steps; streaming
+    stores, which the library picks at this size), checked where the oracle
+    can compute nodes exactly from a window: after N steps a node depends only
+    on the state within N lattice units (one-node pulls, node-local closure,
+    enthalpy update and extrapolations, a restart from the nearest
+    neighbours).  The oracle runs on a window along the hot wall, with
+    adiabatic walls on its three inner sides (H = 4096, the window's slice of
+    K); every node farther than N from those sides is exact, and those nodes
+    must match the GPU run of the whole lattice at the parity bounds."""
+    from paper_1503_08406_amd.dmrt import Solver
+    n, N = 4096, 384
+    wx, wy, y0 = N + 100, 2 * N + 100, n // 2 - N - 50
+    case = W.cavity(nx=n, ny=n, steps=N)
+    s = Solver(case, graph_steps=64)
+    _say("cavity 4096^2, %d steps" % N)
+    s.step(N)
+    Fg = s.fields()
+    s.close()
+    win = W.make_case("cavity_window", wx, wy, [1, 2, 2, 2], [1.0, 0.0, 0.0, 0.0],
+                      Ra=case["Ra"], Da=case["Da"], Pr=case["Pr"], Ste=case["Ste"],
+                      eps=case["eps"][y0:y0 + wy, :wx], K=case["K"][y0:y0 + wy, :wx],
+                      H=float(n), **case["opts"])
+    o = oracle_from_case(win)
+    _say("oracle window %dx%d, %d steps" % (wx, wy, N))
+    o.step(N)
+    Fo = o.fields()
+    ex, ey = slice(0, wx - N), slice(N, wy - N)  # exact nodes of the window
+    fg = {k: Fg[k][y0:y0 + wy][ey, ex] for k in ("T", "ux", "uy", "fl")}
+    fo = {k: Fo[k][ey, ex] for k in ("T", "ux", "uy", "fl")}
+    e = assert_fields_close(fg, fo, label="4096^2 window")
+    _say("4096^2 window errors", {k: float("%.3g" % v) for k, v in e.items()})
+    assert (fo["fl"] > 0).any() and np.abs(fo["uy"]).max() > 0  # melting and flow
+
+
 def test_cavity_full_length_against_oracle_golden():
     """The full benchmark workload (1024x1024, 100000 steps, graph replay as
     benchmarked) against the oracle's own 100000-step run: after 20000,
