@@ -176,7 +176,9 @@ int dmrt_fields(dmrt_t *h, float *T, float *ux, float *uy, float *fl);
 /* Replace the state with the pre-collision populations f[9][ny][nx],
  * g[5][ny][nx] and liquid fraction fl[ny][nx].  f may be NULL (rest
  * equilibrium w_i rho0), g may be NULL (g^eq at T_init), fl may be NULL
- * (f_l(T) of Eq. 42 with T = sum g).  The time counter is not changed. */
+ * (f_l(T) of Eq. 42 with T = sum g).  The time counter is not changed.
+ * A given f switches a handle created without buoyancy (Ra = 0) to the
+ * flow kernels for good, so that the given velocity field evolves. */
 int dmrt_set_state(dmrt_t *h, const float *f, const float *g, const float *fl);
 
 /* Post-collision populations of the current time step: fpost[9][ny][nx]
@@ -197,7 +199,8 @@ int dmrt_step_counted(dmrt_t *h, int64_t n, int32_t *max_it, double *mean_it);
 /* Checkpoint: dmrt_state_bytes() bytes hold the complete state and the time
  * counter; dmrt_save writes them to a host buffer of capacity cap
  * (DMRT_ESIZE if smaller), dmrt_load restores them into a handle created
- * with the same grid (DMRT_EINVAL otherwise). */
+ * with the same grid (DMRT_EINVAL otherwise).  A checkpoint of a handle that
+ * ran the flow kernels switches the loading handle to them as well. */
 int64_t dmrt_state_bytes(const dmrt_t *h);
 int dmrt_save(dmrt_t *h, void *buf, size_t cap);
 int dmrt_load(dmrt_t *h, const void *buf, size_t n);
