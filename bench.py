@@ -82,6 +82,26 @@ def active_cell_steps(case, steps, samples, **over):
     return tot, pts[-1][1]
 
 
+def repeats(case, steps, n=5, **over):
+    """The first `steps` steps of the workload timed n times, each on a fresh
+    solver (HIP events on its stream): per-step kernel times and their
+    median, as a measure of the run-to-run spread."""
+    import torch
+    from paper_1503_08406_amd.dmrt import Solver
+    ms = []
+    for _ in range(n):
+        s = Solver(case, **over)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s.stream)
+        s.step(steps)
+        ev1.record(s.stream)
+        s.sync()
+        ms.append(ev0.elapsed_time(ev1) / steps)
+        s.close()
+    return {"n": n, "steps": steps, "kernel_ms": [round(v, 6) for v in ms],
+            "median_kernel_ms": round(sorted(ms)[n // 2], 6)}
+
+
 def plain_copy(nbytes, copies=64, reps=10):
     """What a plain device copy reaches for the same bytes: copies back and
     forth between two buffers of nbytes/2 each (each copy reads half and
@@ -425,6 +445,7 @@ def main():
 
     cp = plain_copy(traffic or bytes_per_launch)
     cp["frac_of_copy"] = round(cp["us"] / (kern_ms * 1e3), 3)
+    rep = repeats(case, min(args.steps, 10000), **over)
 
     out = {
         "metric": "MLUPS (flow+thermal)",
@@ -454,7 +475,7 @@ def main():
                      "bytes_per_launch": round(bytes_per_launch),
                      "fluid_fraction_mean": round(fluid_frac, 5),
                      "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID},
-                     "plain_copy": cp},
+                     "plain_copy": cp, "repeats": rep},
         "phase": {"active_cells_end": int(act_end), "front_mean_end": round(d["front_mean"], 3)},
     }
     if not args.no_batch:
