@@ -782,3 +782,37 @@ def test_domain_of_dependence_is_one_node_per_step():
     rows = np.where(d[:, ex].any(1))[0]
     cols = np.where(d[ey].any(0))[0]
     assert rows[rows < N].max() >= 0.7 * N and cols.min() <= wx - 0.7 * N
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("convective", [1, 0])
+@pytest.mark.parametrize("sigma", [1.0, 1.5])
+def test_temperature_mode_is_advected_at_u_over_sigma(oracle_mod, axis, convective, sigma):
+    """Eq. (3) in a periodic liquid box carried by a uniform velocity (clear
+    fluid, no force, so the flow stays uniform): a sinusoidal temperature
+    mode moves at u/sigma when the convective term is on (the u terms of
+    Eqs. 34 and 39) and stays in place when it is off, and decays at
+    (alpha_e/sigma) q^2 either way.  Along x with u > 0 and along y with
+    v < 0."""
+    n, m, steps, amp, U = 64, 4, 1000, 0.1, 0.01
+    nx, ny = (n, m) if axis == 0 else (m, n)
+    u0, v0 = (U, 0.0) if axis == 0 else (0.0, -U)
+    c = W.make_case("advect", nx, ny, [0] * 4, [0] * 4, Ra=0, Da=1e-2, Pr=1, Ste=1, eps=1.0,
+                    T_init=0.0, T_s=-6, T_l=-5, alpha_l=0.02, convective=convective,
+                    sigma_s=sigma, sigma_l=sigma)
+    o = oracle_from_case(c)
+    q = 2 * math.pi / n
+    mode = amp * np.sin(q * np.arange(n))
+    T = np.broadcast_to(mode, (ny, nx)) if axis == 0 else np.broadcast_to(mode[:, None], (ny, nx))
+    f = np.broadcast_to(oracle_mod.feq(1.0, u0, v0, 1.0)[:, None, None], (9, ny, nx))
+    g = np.stack([oracle_mod.geq(t, u0, v0, sigma) for t in T.ravel()], 1).reshape(5, ny, nx)
+    o.set_state(f, g, np.ones((ny, nx)))
+    o.step(steps)
+    F = o.fields()
+    assert np.abs(F["ux"] - u0).max() < 1e-14 and np.abs(F["uy"] - v0).max() < 1e-14
+    Tm = F["T"].mean(axis=0 if axis == 0 else 1)
+    c1 = np.fft.rfft(Tm)[1] / np.fft.rfft(mode)[1]
+    shift = -np.angle(c1) / q
+    assert abs(shift - convective * (u0 + v0) * steps / sigma) < 0.01
+    decay = math.exp(-o.derived["alpha_l"] / sigma * q * q * steps)
+    assert abs(abs(c1) / decay - 1) < 2e-3
