@@ -816,3 +816,37 @@ def test_temperature_mode_is_advected_at_u_over_sigma(oracle_mod, axis, convecti
     assert abs(shift - convective * (u0 + v0) * steps / sigma) < 0.01
     decay = math.exp(-o.derived["alpha_l"] / sigma * q * q * steps)
     assert abs(abs(c1) / decay - 1) < 2e-3
+
+
+@pytest.mark.parametrize("phi,Da", [(1.0, 1e6), (0.5, 1e6), (0.3, 1e6), (0.5, 1e-2)])
+def test_porous_taylor_green_vortex(oracle_mod, phi, Da):
+    """Eq. (2) with uniform porosity, no gravity, no Forchheimer term: the
+    Taylor-Green vortex u = U(-cos kx sin ky, sin kx cos ky) e^{-gamma t}
+    solves it exactly with gamma = 2 nu_e k^2 + phi nu / K, its convective
+    term (u.grad)(u/phi) balanced by the pressure gradient, so that
+    c_s^2 (rho - 1) = -(U^2 e^{-2 gamma t} / (4 phi)) (cos 2kx + cos 2ky).
+    The density amplitude pins the 1/phi of the quadratic terms of the
+    equilibria (Eqs. 19, 29); on a 32^2 lattice both amplitudes agree to
+    0.6 %, a discretisation error that falls four-fold on 64^2."""
+    n, U, steps = 32, 0.01, 200
+    c = W.make_case("tg", n, n, [0] * 4, [0] * 4, Ra=0, Da=Da, Pr=1, Ste=1, eps=phi, Feps=0.0,
+                    H=float(n), T_init=0.0, T_s=-6, T_l=-5, alpha_l=0.02, convective=1)
+    o = oracle_from_case(c)
+    d = o.derived
+    k = 2 * math.pi / n
+    X, Y = np.meshgrid(np.arange(n), np.arange(n))
+    u = -U * np.cos(k * X) * np.sin(k * Y)
+    v = U * np.sin(k * X) * np.cos(k * Y)
+    drho = -3 * U * U / (4 * phi) * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    f = np.stack([oracle_mod.feq(1 + r, a, b, phi) for r, a, b in zip(drho.ravel(), u.ravel(),
+                                                                      v.ravel())], 1)
+    g = np.stack([oracle_mod.geq(0.0, a, b, 1.0) for a, b in zip(u.ravel(), v.ravel())], 1)
+    o.set_state(f.reshape(9, n, n), g.reshape(5, n, n), np.ones((n, n)))
+    o.step(steps)
+    F = o.fields()
+    Ut = U * math.exp(-(2 * d["nu_e"] * k * k + phi * d["nu_l"] / (Da * n * n)) * steps)
+    shape = np.cos(k * X) * np.sin(k * Y)
+    u_amp = -(F["ux"] * shape).sum() / (shape ** 2).sum()
+    r_amp = -((F["rho"] - 1) * np.cos(2 * k * X)).sum() / (np.cos(2 * k * X) ** 2).sum()
+    assert abs(u_amp / Ut - 1) < 1e-2
+    assert abs(r_amp / (3 * Ut * Ut / (4 * phi)) - 1) < 1.5e-2
