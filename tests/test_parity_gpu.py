@@ -270,6 +270,38 @@ def test_advected_temperature_mode_matches_oracle(oracle_mod, axis, convective):
     assert abs(shift - convective * (u0 + v0) * steps / sigma) < 0.01
 
 
+def test_porous_taylor_green_vortex_matches_oracle(oracle_mod):
+    """The porous Taylor-Green vortex (porosity 0.5, Darcy drag, no gravity;
+    the given velocity field switches the handle to the flow kernels): GPU
+    against the oracle, and the velocity amplitude against
+    U exp(-(2 nu_e k^2 + phi nu / K) t)."""
+    n, U, steps, phi, Da = 32, 0.01, 200, 0.5, 1e-2
+    case = W.make_case("tg", n, n, [0] * 4, [0] * 4, Ra=0, Da=Da, Pr=1, Ste=1, eps=phi, Feps=0.0,
+                       H=float(n), T_init=0.0, T_s=-6, T_l=-5, alpha_l=0.02, convective=1)
+    k = 2 * math.pi / n
+    X, Y = np.meshgrid(np.arange(n), np.arange(n))
+    u = -U * np.cos(k * X) * np.sin(k * Y)
+    v = U * np.sin(k * X) * np.cos(k * Y)
+    drho = -3 * U * U / (4 * phi) * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    f = np.stack([oracle_mod.feq(1 + r, a, b, phi) for r, a, b in zip(drho.ravel(), u.ravel(),
+                                                                      v.ravel())], 1)
+    g = np.stack([oracle_mod.geq(0.0, a, b, 1.0) for a, b in zip(u.ravel(), v.ravel())], 1)
+    f, g, fl = f.reshape(9, n, n), g.reshape(5, n, n), np.ones((n, n))
+    s, o = pair(case)
+    s.set_state(f.astype(np.float32), g.astype(np.float32), fl.astype(np.float32))
+    o.set_state(f, g, fl)
+    _say("porous Taylor-Green vortex")
+    s.step(steps)
+    o.step(steps)
+    Fg, Fo = s.fields(), o.fields()
+    du = max(np.abs(Fg["ux"] - Fo["ux"]).max(), np.abs(Fg["uy"] - Fo["uy"]).max())
+    assert du / np.abs(Fo["ux"]).max() < 1e-3
+    d = o.derived
+    Ut = U * math.exp(-(2 * d["nu_e"] * k * k + phi * d["nu_l"] / (Da * n * n)) * steps)
+    shape = np.cos(k * X) * np.sin(k * Y)
+    assert abs(-(Fg["ux"] * shape).sum() / (shape ** 2).sum() / Ut - 1) < 1e-2
+
+
 def test_graph_replay_equals_plain_launches():
     """Steps replayed from a captured HIP graph give the same bits as plain
     launches, across several replays with eager work in between."""
