@@ -850,3 +850,39 @@ def test_porous_taylor_green_vortex(oracle_mod, phi, Da):
     r_amp = -((F["rho"] - 1) * np.cos(2 * k * X)).sum() / (np.cos(2 * k * X) ** 2).sum()
     assert abs(u_amp / Ut - 1) < 1e-2
     assert abs(r_amp / (3 * Ut * Ut / (4 * phi)) - 1) < 1.5e-2
+
+
+@pytest.mark.parametrize("phi", [0.5, 0.8])
+def test_porous_layer_heated_from_below_onset(oracle_mod, phi):
+    """Eqs. (2)-(4) coupled through the buoyancy force: a fluid-saturated
+    porous layer between a hot bottom wall and a cold top wall is stable
+    below and unstable above the Horton-Rogers-Lapwood threshold
+    Ra_D = g beta dT K H / (nu alpha_e) = 4 pi^2 of Darcy's law (critical
+    wavelength 2H).  At Da = 1e-3 the Brinkman layers at the no-slip walls
+    raise the threshold by about 10 %: the convective mode (wavelength 2H)
+    decays at 0.9 x 4 pi^2 and grows at 1.25 x 4 pi^2.  A wrong porosity
+    factor in the drag or the buoyancy, a wrong alpha_e or a wrong sign of
+    the buoyancy moves the threshold out of that bracket."""
+    ny, Da = 16, 1e-3
+    H, nx = ny + 1.0, 2 * (ny + 1)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    shape = np.cos(2 * math.pi * X / nx) * np.sin(math.pi * (Y + 1) / H)
+    L = oracle_mod.lattice()
+
+    def mode_rate(RaD):
+        c = W.make_case("onset", nx, ny, [0, 0, 1, 1], [0, 0, 1.0, 0.0], Ra=RaD / Da, Da=Da, Pr=1,
+                        Ste=1, eps=phi, Feps=0.0, H=H, T_init=0.0, T_s=-6, T_l=-5,
+                        convective=1, T0=0.5, Ma=0.3)
+        o = oracle_from_case(c)
+        T = 1 - (Y + 1) / H + 1e-3 * shape
+        f = np.broadcast_to(np.asarray(L["w9"])[:, None, None], (9, ny, nx))
+        o.set_state(f, np.asarray(L["w5"])[:, None, None] * T[None], np.ones((ny, nx)))
+        amp = []
+        for t in (10000, 30000):
+            o.step(t - o.time)
+            amp.append((o.fields()["uy"] * shape).sum() / (shape ** 2).sum())
+        assert amp[0] * amp[1] > 0  # the same mode, not a sign change of noise
+        return math.log(abs(amp[1] / amp[0])) / 20000
+
+    assert mode_rate(0.9 * 4 * math.pi ** 2) < -5e-5
+    assert mode_rate(1.25 * 4 * math.pi ** 2) > 5e-5
