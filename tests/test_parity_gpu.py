@@ -302,6 +302,37 @@ def test_porous_taylor_green_vortex_matches_oracle(oracle_mod):
     assert abs(-(Fg["ux"] * shape).sum() / (shape ** 2).sum() / Ut - 1) < 1e-2
 
 
+def test_porous_layer_onset_matches_oracle(oracle_mod):
+    """A porous layer heated from below above the convection threshold
+    (Ra_D = 1.25 x 4 pi^2, Da = 1e-3, porosity 0.5): the convective mode grows
+    from a small perturbation on the GPU (graph replay) as in the oracle."""
+    ny, Da, phi = 16, 1e-3, 0.5
+    H, nx = ny + 1.0, 2 * (ny + 1)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    shape = np.cos(2 * math.pi * X / nx) * np.sin(math.pi * (Y + 1) / H)
+    case = W.make_case("onset", nx, ny, [0, 0, 1, 1], [0, 0, 1.0, 0.0],
+                       Ra=1.25 * 4 * math.pi ** 2 / Da, Da=Da, Pr=1, Ste=1, eps=phi, Feps=0.0, H=H,
+                       T_init=0.0, T_s=-6, T_l=-5, convective=1, T0=0.5, Ma=0.3)
+    T = 1 - (Y + 1) / H + 1e-3 * shape
+    f = np.broadcast_to(np.asarray(oracle_mod.lattice()["w9"])[:, None, None], (9, ny, nx))
+    g = np.asarray(oracle_mod.lattice()["w5"])[:, None, None] * T[None]
+    fl = np.ones((ny, nx))
+    s, o = pair(case, gpu_over=dict(graph_steps=64))
+    s.set_state(f.astype(np.float32), g.astype(np.float32), fl.astype(np.float32))
+    o.set_state(f, g, fl)
+    amps = []
+    for t in (10000, 30000):
+        _say("porous layer onset, step", t)
+        s.step(t - s.time)
+        o.step(t - o.time)
+        Fg, Fo = s.fields(), o.fields()
+        assert_fields_close(Fg, Fo, label="onset %d" % t)
+        amps.append([(F["uy"] * shape).sum() / (shape ** 2).sum() for F in (Fg, Fo)])
+    rg = math.log(amps[1][0] / amps[0][0]) / 20000
+    ro = math.log(amps[1][1] / amps[0][1]) / 20000
+    assert rg > 5e-5 and abs(rg - ro) < 1e-3 * ro
+
+
 def test_graph_replay_equals_plain_launches():
     """Steps replayed from a captured HIP graph give the same bits as plain
     launches, across several replays with eager work in between."""
