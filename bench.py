@@ -82,6 +82,41 @@ def active_cell_steps(case, steps, samples, **over):
     return tot, pts[-1][1]
 
 
+def small_configs():
+    """The two small validation workloads in full, on the GPU (graph replay
+    of 64 steps) and on the FP64 oracle (up to 16 threads): the conduction
+    slab of Sec. 4.1 (256x4, 5000 steps) and the corner of Sec. 4.2 (256x256,
+    20000 steps).  Wall-clock seconds of each; context for the oracle figure,
+    not a throughput claim (both are far too small to fill the GPU)."""
+    import torch
+    from paper_1503_08406_amd import workloads as W
+    from paper_1503_08406_amd.dmrt import Solver
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from conftest import oracle_from_case
+    cores = min(16, len(os.sched_getaffinity(0)))
+    out = {}
+    for name, case in (("conduction_slab_256x4", W.conduction_slab()),
+                       ("corner_256x256", W.corner())):
+        steps = case["steps"]
+        s = Solver(case, graph_steps=64)
+        s.sync()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        g = time.perf_counter() - t
+        s.close()
+        o = oracle_from_case(case, nthreads=cores)
+        t = time.perf_counter()
+        o.step(steps)
+        c = time.perf_counter() - t
+        cells = case["nx"] * case["ny"]
+        out[name] = {"steps": steps, "gpu_s": round(g, 4), "oracle_s": round(c, 3),
+                     "oracle_cores": cores, "gpu_mlups": round(cells * steps / g / 1e6, 1),
+                     "oracle_mlups": round(cells * steps / c / 1e6, 2)}
+    return out
+
+
 def repeats(case, steps, n=5, **over):
     """The first `steps` steps of the workload timed n times, each on a fresh
     solver (HIP events on its stream): per-step kernel times and their
@@ -486,6 +521,7 @@ def main():
         out["hbm_point"] = hbm_point()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
+        out["small_configs"] = small_configs()
     print(json.dumps(out), flush=True)
     return 0
 
