@@ -31,6 +31,7 @@ BYTES_SOLID_BATCH = 2 * 5 * 4 + 2 * 4            # 48
 KERNEL_SRC = [os.path.join(ROOT, "paper_1503_08406_amd", "csrc", n)
               for n in ("dmrt_step.hip", "dmrt_node.h", "dmrt_device.h", "dmrt_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic_cavity1024.json")
+TRAFFIC_FILE_4096 = os.path.join(ROOT, "profiles", "step_traffic_cavity4096.json")
 
 
 def kernel_hash():
@@ -196,6 +197,15 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
     bpl = (BYTES_FLUID * ff + BYTES_SOLID * (1 - ff)) * cells
     cp = plain_copy(bpl)
     cp["frac_of_copy"] = round(cp["us"] / (kern_ms * 1e3), 3)
+    # measured HBM traffic of this kernel at this size (rocprofv3 FETCH_SIZE /
+    # WRITE_SIZE over steps 10..210), valid while the kernel source is the one
+    # that was measured; its liquid fraction is stated beside it
+    traffic = None
+    if n == 4096 and os.path.exists(TRAFFIC_FILE_4096):
+        tr = json.load(open(TRAFFIC_FILE_4096))
+        if tr.get("kernel_sha") == kernel_hash():
+            traffic = {"bytes": tr["bytes_per_launch"], "fluid_fraction": tr["fluid_fraction"],
+                       "GBps": round(tr["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9, 1)}
     return {"workload": "the same cavity at %dx%d (%.2f GB of state), steps %d..%d"
                         % (n, n, cells * 148 / 1e9, warmup, warmup + steps),
             "value": round(cells * steps / wall / 1e6, 2), "unit": "MLUPS",
@@ -203,7 +213,8 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
             "roofline": {"bound": "hbm", "achieved": round(bpl / (kern_ms * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                          "frac": round(bpl / (kern_ms * 1e-3) / HBM_PEAK, 4),
-                         "fluid_fraction_mean": round(ff, 5), "plain_copy": cp},
+                         "fluid_fraction_mean": round(ff, 5), "traffic": traffic,
+                         "plain_copy": cp},
             "nonfinite": int(d["nonfinite"])}
 
 
