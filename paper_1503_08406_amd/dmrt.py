@@ -169,9 +169,11 @@ def _ptr(a):
     if a is None:
         return None
     if hasattr(a, "data_ptr"):
-        assert a.dtype.__str__() == "torch.float32" and a.is_contiguous()
+        if str(a.dtype) != "torch.float32" or not a.is_contiguous():
+            raise TypeError("expected a contiguous float32 tensor, got %s" % (a.dtype,))
         return C.c_void_p(a.data_ptr())
-    assert a.dtype == np.float32 and a.flags.c_contiguous
+    if a.dtype != np.float32 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous float32 array, got %s" % (a.dtype,))
     return a.ctypes.data_as(C.c_void_p)
 
 
