@@ -532,7 +532,7 @@ def main():
         out["hbm_point"] = hbm_point()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
-        out["small_configs"] = small_configs()
+        out["cpu_baseline"]["small_configs"] = small_configs()
     print(json.dumps(out), flush=True)
     return 0
 
