@@ -109,6 +109,35 @@ def test_conduction_slab_full_size():
     assert abs(d["front_mean"] - front_rows(Fo["fl"]).mean()) < 0.5
 
 
+@pytest.mark.parametrize("half_range,Ste", [(1e-4, 1.0), (1e-4, 0.05), (0.2, 0.05)])
+def test_conduction_slab_mushy_range_extremes(half_range, Ste):
+    """Sec. 4.1 slab with a nearly sharp (+-1e-4) and a wide (+-0.2) mushy
+    range, at Stefan numbers 1 and 0.05: the enthalpy iteration on the GPU
+    against the oracle, and the front against the Neumann solution where the
+    range is sharp (Eqs. 43-46, latent heat phi L_a)."""
+    case = W.make_case("slab_mushy", 256, 4, [1, 2, 0, 0], [1.0, 0.0, 0.0, 0.0], Ra=0.0,
+                       Da=1e-4, Pr=1.0, Ste=Ste, eps=0.5, T_init=-1.0, T_s=-half_range,
+                       T_l=half_range, alpha_l=0.02, convective=0)
+    s, o = pair(case, gpu_over=dict(fl_tol=1e-7))
+    _say("slab mushy range", half_range, "Ste", Ste)
+    s.step(3000)
+    o.step(3000)
+    Fg, Fo = s.fields(), o.fields()
+    assert_fields_close(Fg, Fo, u_floor=1e-12, label="slab %g %g" % (half_range, Ste))
+    if half_range < 1e-3:
+        # Neumann: theta_w = 1, theta_i = -1, melting at 0, latent heat phi/St
+        St_e = Ste / 0.5
+        f = lambda lam: (math.exp(-lam * lam) / math.erf(lam)
+                         - math.exp(-lam * lam) / math.erfc(lam)
+                         - lam * math.sqrt(math.pi) / St_e)
+        lo, hi = 1e-6, 3.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if f(mid) > 0 else (lo, mid)
+        xm = 2 * lo * math.sqrt(0.02 * 3000)
+        assert np.abs(front_rows(Fg["fl"]) - xm).max() < 0.5
+
+
 def test_corner_reduced_matches_oracle():
     """Sec. 4.2 setting at 96x96 for 3000 steps: elementwise parity and the
     exact x <-> y symmetry of the GPU result."""
