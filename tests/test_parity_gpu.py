@@ -167,6 +167,26 @@ def test_convective_cavity_matches_oracle(nx, ny, Ra, steps):
     assert e["umax"] > 1e-4 and (Fo["fl"] > 0).sum() > 100
 
 
+def test_convective_cavity_freezing_matches_oracle():
+    """The reverse of the melting cavity: a liquid porous cavity (initial
+    theta 0.8, melting at 0.5 +- 0.02) convecting between a hot left wall
+    (theta 1) and a cold right wall (theta 0), so that the liquid freezes at
+    the cold wall while it flows: nodes leave the flow domain and the solid
+    becomes a no-slip boundary for the liquid."""
+    case = W.make_case("freezing", 100, 72, [1, 1, 2, 2], [1.0, 0.0, 0.0, 0.0], Ra=1e5, Da=5e-3,
+                       Pr=1.0, Ste=0.5, eps=0.45, H=72, T_init=0.8, T_s=0.48, T_l=0.52,
+                       convective=1)
+    s, o = pair(case)
+    for k in range(4):
+        _say("freezing cavity, step", 750 * (k + 1))
+        s.step(750)
+        o.step(750)
+        Fg, Fo = s.fields(), o.fields()
+        e = assert_fields_close(Fg, Fo, label="freezing step %d" % s.time)
+    solid = (Fo["fl"] == 0).sum()
+    assert e["umax"] > 1e-4 and solid > 100 and (Fo["fl"] > 0).sum() > 100
+
+
 def test_degenerate_lattices():
     """Edge cases: a single periodic node, a one-node-wide channel between
     walls, a lattice that stays fully solid and one that is fully liquid."""
