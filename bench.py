@@ -275,7 +275,7 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
             "liquid_cells_end": int(liq.sum())}
 
 
-def adjoint_timing(warm=200):
+def adjoint_timing(warm=200, steps=0):
     """The inverse-problem workload (512x512 cavity, Gaussian-random-field
     log K seed 1, target run seed 2, 2000 steps): wall time of the plain
     forward run, of the recorded forward run (checkpoints every ceil(sqrt n)
@@ -286,7 +286,7 @@ def adjoint_timing(warm=200):
     from paper_1503_08406_amd import workloads as W
     from paper_1503_08406_amd.dmrt import Solver
     case, target = W.adjoint_cavity(), W.adjoint_cavity(seed=2)
-    steps = case["steps"]
+    steps = steps or case["steps"]
     t = Solver(target, graph_steps=64)
     t.step(steps)
     Ft = t.fields()
@@ -317,7 +317,7 @@ def adjoint_timing(warm=200):
     s.close()
     return {"workload": "inverse problem: 512x512 cavity (Sec. 4.3 setting), Ra=1e5 Da=1e-3 Ste=1 "
                         "eps=0.4, log K = log(Da H^2) + 0.5 GRF(corr 32, seed 1), target run "
-                        "seed 2, L = 1/2 sum((f_l - f_l*)^2 + (T - T*)^2) after 2000 steps",
+                        "seed 2, L = 1/2 sum((f_l - f_l*)^2 + (T - T*)^2) after %d steps" % steps,
             "steps": steps, "forward_ms": round(fwd, 3), "record_ms": round(rec, 3),
             "adjoint_ms": round(adj, 3), "adjoint_first_call_ms": round(adj_first, 3),
             "adjoint_over_forward": round(adj / fwd, 3),
@@ -416,6 +416,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-cavity measurement")
     ap.add_argument("--batch-steps", type=int, default=0, help="batched steps (0: the workload's)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--adjoint-steps", type=int, default=0,
+                    help="steps of the adjoint run (0: the workload's 2000; fewer for profiling)")
     ap.add_argument("--no-hbm", action="store_true",
                     help="skip the 4096^2 point (state beyond the Infinity Cache)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -527,7 +529,7 @@ def main():
     if not args.no_batch:
         out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint)
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_timing()
+        out["adjoint"] = adjoint_timing(steps=args.adjoint_steps)
     if not args.no_hbm:
         out["hbm_point"] = hbm_point()
     if not args.no_cpu:
