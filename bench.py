@@ -42,7 +42,10 @@ def kernel_hash():
 
 
 def cpu_baseline(case, budget_s=15.0):
-    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    """The FP64 oracle as it stands, on a bounded sample of the same workload
+    (from its initial state: the oracle takes minutes to reach the GPU's
+    timed window), on the host threads this process may use (at most 16, the
+    CPU share of a one-GPU machine) and on one thread."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from conftest import oracle_from_case
     cores = min(16, len(os.sched_getaffinity(0)))
@@ -60,6 +63,8 @@ def cpu_baseline(case, budget_s=15.0):
     o1.step(3)
     el1 = time.perf_counter() - t
     return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "host_cores_available": len(os.sched_getaffinity(0)),
+            "host_cpu_count": os.cpu_count(),
             "value_1_thread": round(cells * 3 / el1 / 1e6, 3),
             "kind": "oracle",
             "sample": "steps 5..%d of the %dx%d cavity from its initial state (FP64 oracle, "
@@ -118,15 +123,37 @@ def small_configs():
     return out
 
 
-def repeats(case, steps, n=5, **over):
-    """The first `steps` steps of the workload timed n times, each on a fresh
-    solver (HIP events on its stream): per-step kernel times and their
-    median, as a measure of the run-to-run spread."""
+def window_accounting(case, buf, steps, samples, **over):
+    """Untimed replay of a timed window from its starting checkpoint `buf`:
+    the integral over the window of the number of cells where the flow is
+    solved (trapezoid over at most `samples` points) and the count at its
+    end."""
+    from paper_1503_08406_amd.dmrt import Solver
+    s = Solver(case, **over)
+    s.load(buf)
+    t0 = s.time
+    samples = max(1, min(samples, steps))
+    pts = [(0, s.diag()["active"])]
+    for k in range(1, samples + 1):
+        tgt = steps * k // samples
+        s.step(t0 + tgt - s.time)
+        pts.append((tgt, s.diag()["active"]))
+    s.close()
+    tot = sum(0.5 * (a0 + a1) * (t1 - t0_) for (t0_, a0), (t1, a1) in zip(pts, pts[1:]))
+    return tot, pts[-1][1]
+
+
+def repeats(case, buf, steps, n=5, **over):
+    """The timed window (`steps` steps from the checkpoint `buf`) timed n
+    more times, each on a fresh solver loaded from the checkpoint (HIP events
+    on its stream): per-step kernel times and their median."""
     import torch
     from paper_1503_08406_amd.dmrt import Solver
     ms = []
     for _ in range(n):
         s = Solver(case, **over)
+        s.load(buf)
+        s.sync()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(s.stream)
         s.step(steps)
@@ -215,6 +242,49 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
                          "frac": round(bpl / (kern_ms * 1e-3) / HBM_PEAK, 4),
                          "fluid_fraction_mean": round(ff, 5), "traffic": traffic,
                          "plain_copy": cp},
+            "nonfinite": int(d["nonfinite"])}
+
+
+def flow_point(n=4096, steps=256, warmup=64, graph_steps=64):
+    """The cavity workload at n x n started liquid (initial theta 0.5, above
+    the liquidus), so that the flow part of the step (D2Q9 pulls, closure,
+    collision) runs at nearly every node, on a state far beyond the Infinity
+    Cache: the HBM roofline of the fluid byte model (132 B per node)."""
+    import torch
+    from paper_1503_08406_amd import workloads as W
+    from paper_1503_08406_amd.dmrt import Solver
+    case = W.cavity(nx=n, ny=n, steps=steps, T_init=0.5)
+    s = Solver(case, graph_steps=graph_steps)
+    s.step(warmup)
+    s.sync()
+    buf = s.save()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(s.stream)
+    s.step(steps)
+    ev1.record(s.stream)
+    s.sync()
+    wall = time.perf_counter() - t0
+    kern_ms = ev0.elapsed_time(ev1) / steps
+    d = s.diag()
+    s.close()
+    act, act_end = window_accounting(case, buf, steps, 16, graph_steps=graph_steps)
+    rep = repeats(case, buf, steps, n=3, graph_steps=graph_steps)
+    del buf
+    cells = n * n
+    ff = act / (cells * steps)
+    bpl = (BYTES_FLUID * ff + BYTES_SOLID * (1 - ff)) * cells
+    med = rep["median_kernel_ms"]
+    return {"workload": "the same cavity at %dx%d started liquid (initial theta 0.5), steps "
+                        "%d..%d" % (n, n, warmup, warmup + steps),
+            "value": round(cells * steps / wall / 1e6, 2), "unit": "MLUPS",
+            "kernel_ms": round(kern_ms, 6),
+            "roofline": {"bound": "hbm", "achieved": round(bpl / (med * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": round(bpl / (med * 1e-3) / HBM_PEAK, 4),
+                         "bytes_per_launch": round(bpl), "fluid_fraction_mean": round(ff, 5),
+                         "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID},
+                         "repeats": rep},
             "nonfinite": int(d["nonfinite"])}
 
 
@@ -358,11 +428,16 @@ def ablation(horizons=((0.04, True), (0.457, True), (1.829, False)), graph_steps
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from conftest import front_rows
 
+    from paper_1503_08406_amd.dmrt import derive
     torch.cuda.set_device(0)
     case = W.gallium_cavity()
+    # time steps of a Fourier number t alpha_l / H^2, alpha_l from the
+    # library's Sec. 4.3 mapping of (Ra, Pr, Ma, H)
+    alpha_l = derive(case["nx"], case["ny"], case["Ra"], case["Da"], case["Pr"], case["Ste"],
+                     H=case["H"], **case["opts"])["alpha_l"]
     ref = {}
     for fo, with_r2 in horizons:
-        steps = W.gallium_fourier_steps(case, fo)
+        steps = int(round(fo * case["H"] ** 2 / alpha_l))
         for name, over in ABLATION:
             if over.get("latent_mode") and not with_r2:
                 continue  # R2 sweeps the whole lattice many times a step
@@ -399,8 +474,13 @@ def ablation(horizons=((0.04, True), (0.457, True), (1.829, False)), graph_steps
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100000)
-    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=2000, help="timed steps")
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps right before the timed window")
+    ap.add_argument("--start", type=int, default=50000,
+                    help="untimed steps from the initial state to the timed window (half of "
+                         "the workload's 100000, so that the window sees the melted, "
+                         "convecting cavity)")
     ap.add_argument("--n", type=int, default=1024, help="lattice side")
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--block-rows", type=int, default=0, help="step-kernel block rows (0: auto)")
@@ -412,14 +492,13 @@ def main():
                     help="cache policy of the state stores: 0 by working set, 1 plain, "
                          "2 write-through, 3 streaming")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--no-account", action="store_true", help="skip the phase accounting replay")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-cavity measurement")
     ap.add_argument("--batch-steps", type=int, default=0, help="batched steps (0: the workload's)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--adjoint-steps", type=int, default=0,
                     help="steps of the adjoint run (0: the workload's 2000; fewer for profiling)")
     ap.add_argument("--no-hbm", action="store_true",
-                    help="skip the 4096^2 point (state beyond the Infinity Cache)")
+                    help="skip the 4096^2 points (state beyond the Infinity Cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--ablation", action="store_true",
@@ -429,8 +508,8 @@ def main():
                     help="with --ablation: one horizon, this Fourier number, all readings")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: runs on one GPU only; --gpus %d is not supported"
-              % args.gpus, file=sys.stderr)
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported (the "
+              "multi-GPU design is described, not built)" % args.gpus, file=sys.stderr)
         return 2
     if args.ablation:
         return ablation(((args.ablation_fo, True),)) if args.ablation_fo > 0 else ablation()
@@ -440,7 +519,8 @@ def main():
     from paper_1503_08406_amd.dmrt import Solver
 
     torch.cuda.set_device(0)
-    case = W.cavity(nx=args.n, ny=args.n, steps=args.steps, T_init=args.T_init)
+    case = W.cavity(nx=args.n, ny=args.n, steps=args.start + args.warmup + args.steps,
+                    T_init=args.T_init)
     over = dict(graph_steps=args.graph_steps, block_rows=args.block_rows, store_hint=args.store_hint,
                 cells_per_lane=args.cells_per_lane)
 
@@ -451,13 +531,14 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print("copy probe: 3 x 1 GiB device-to-device copies", flush=True)
+        del a, b
 
-    # warm-up on a throw-away solver, then time the workload from t = 0
-    w = Solver(case, **over)
-    w.step(args.warmup)
-    w.sync()
-    w.close()
+    # untimed: advance to the start of the window, then the warm-up steps
     s = Solver(case, **over)
+    s.step(args.start + args.warmup)
+    s.sync()
+    buf = s.save()  # the window's starting state (for the replays below)
+    t_start = s.time
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -470,17 +551,18 @@ def main():
     wall = t1 - t0
     kern_ms = ev0.elapsed_time(ev1) / args.steps
     d = s.diag()
+    s.close()
     assert d["nonfinite"] == 0, "non-finite state after the timed run"
     cells = case["nx"] * case["ny"]
     mlups = cells * args.steps / wall / 1e6
 
-    if args.no_account:
-        act_steps, act_end = float(d["active"]) * args.steps, d["active"]
-    else:
-        act_steps, act_end = active_cell_steps(case, args.steps, 50, **over)
+    act_steps, act_end = window_accounting(case, buf, args.steps, 50, **over)
     fluid_frac = act_steps / (cells * args.steps)
     bytes_per_launch = (BYTES_FLUID * fluid_frac + BYTES_SOLID * (1 - fluid_frac)) * cells
-    achieved = bytes_per_launch / (kern_ms * 1e-3)
+    rep = repeats(case, buf, args.steps, **over)
+    del buf
+    med_ms = rep["median_kernel_ms"]
+    achieved = bytes_per_launch / (med_ms * 1e-3)
     # measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, two
     # phase mixes solved for bytes per solid and per liquid node), valid while
     # the step kernel source is the one that was measured
@@ -492,8 +574,7 @@ def main():
                              tr["bytes_per_cell_fluid"] * fluid_frac) * cells)
 
     cp = plain_copy(traffic or bytes_per_launch)
-    cp["frac_of_copy"] = round(cp["us"] / (kern_ms * 1e3), 3)
-    rep = repeats(case, min(args.steps, 10000), **over)
+    cp["frac_of_copy"] = round(cp["us"] / (med_ms * 1e3), 3)
 
     out = {
         "metric": "MLUPS (flow+thermal)",
@@ -510,28 +591,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": "convection melting in a porous cavity %dx%d (Sec. 4.3 setting): "
                                "Ra=1e6 Da=1e-4 Pr=1 Ste=1 eps=0.4, log-normal K (sigma 0.1, "
-                               "seed 3), initial theta %g, steps 0..%d"
-                               % (args.n, args.n, args.T_init, args.steps),
-                   "nx": args.n, "ny": args.n, "graph_steps": args.graph_steps,
-                   "block_rows": args.block_rows, "cells_per_lane": args.cells_per_lane,
-                   "parallelism": "single GPU"},
+                               "seed 3), initial theta %g, timed steps %d..%d"
+                               % (args.n, args.n, args.T_init, t_start, t_start + args.steps),
+                   "nx": args.n, "ny": args.n, "window_start": t_start,
+                   "graph_steps": args.graph_steps, "block_rows": args.block_rows,
+                   "cells_per_lane": args.cells_per_lane, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": traffic,
-                     "traffic_GBps": None if traffic is None else round(traffic / (kern_ms * 1e-3) / 1e9, 1),
-                     "kernel": "k_step (flow, 4 rows, 1 node per lane)", "kernel_ms": round(kern_ms, 6),
+                     "traffic_GBps": None if traffic is None else round(traffic / (med_ms * 1e-3) / 1e9, 1),
+                     "kernel": "k_step (flow, 4 rows, 1 node per lane)",
+                     "kernel_ms": round(med_ms, 6), "kernel_ms_timed_run": round(kern_ms, 6),
                      "bytes_per_launch": round(bytes_per_launch),
                      "fluid_fraction_mean": round(fluid_frac, 5),
                      "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID},
                      "plain_copy": cp, "repeats": rep},
         "phase": {"active_cells_end": int(act_end), "front_mean_end": round(d["front_mean"], 3)},
     }
-    if not args.no_batch:
-        out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint)
-    if not args.no_adjoint:
-        out["adjoint"] = adjoint_timing(steps=args.adjoint_steps)
     if not args.no_hbm:
         out["hbm_point"] = hbm_point()
+        out["flow_point"] = flow_point()
+    if not args.no_batch:
+        out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint)
+        if "hbm_point" in out:
+            out["batched"]["ratio_to_single_4096"] = round(
+                out["batched"]["value"] / out["hbm_point"]["value"], 4)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_timing(steps=args.adjoint_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
         out["cpu_baseline"]["small_configs"] = small_configs()

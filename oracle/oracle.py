@@ -12,12 +12,17 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dmrt_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_dmrt.so")
+# DMRT_ORACLE_LIB loads another build of the oracle instead (the mutation
+# tests load copies with one planted mistake); nothing is built then.
+_LIB_OVERRIDE = os.environ.get("DMRT_ORACLE_LIB")
 
 PERIODIC, WALL_T, WALL_ADIABATIC = 0, 1, 2
 
 
 def build(force=True):
     """Compile the oracle with gcc (OpenMP).  Always recompiles when force."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
@@ -58,9 +63,9 @@ _IP = C.POINTER(C.c_int)
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not _LIB_OVERRIDE and not os.path.exists(_LIB):
             build(force=False)
-        lib = C.CDLL(_LIB)
+        lib = C.CDLL(_LIB_OVERRIDE or _LIB)
         lib.orc_default_params.argtypes = [C.POINTER(Params)]
         lib.orc_derive.argtypes = [C.POINTER(Params), C.POINTER(Derived)]
         lib.orc_derive.restype = C.c_int

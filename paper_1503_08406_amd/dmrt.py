@@ -210,6 +210,10 @@ class Solver:
         d = Derived()
         _check(_lib.dmrt_get_derived(self._h, C.byref(d)))
         self.derived = {n: getattr(d, n) for n, _ in Derived._fields_}
+        # changes whenever the library's recorded run is replaced or
+        # discarded (record, set_porous), so that a backward pass can tell
+        # whether the recording is still the one its forward pass made
+        self.record_id = 0
 
     @property
     def handle(self):
@@ -291,6 +295,7 @@ class Solver:
         conv = lambda a: None if a is None else np.ascontiguousarray(
             np.broadcast_to(np.asarray(a, dtype=np.float32), shape))
         e, k, f = conv(eps), conv(K), conv(Feps)
+        self.record_id += 1  # the library discards a recorded run here
         _check(_lib.dmrt_set_porous(self._h, _ptr(e), _ptr(k), _ptr(f)))
 
     def reset(self):
@@ -299,6 +304,7 @@ class Solver:
 
     def record(self, n):
         """Advance n steps keeping what dmrt_adjoint needs."""
+        self.record_id += 1
         _check(_lib.dmrt_record(self._h, int(n)))
 
     def adjoint(self, dL_dT=None, dL_dfl=None):
@@ -453,7 +459,11 @@ def melting_run(solver, logK, eps, steps):
     """Differentiable run: (T, f_l) after `steps` steps from the initial state
     of `solver` with per-cell log-permeability logK and porosity eps (torch
     tensors [ny, nx]); gradients flow back to logK and eps through the
-    library's discrete adjoint (checkpointed recomputation)."""
+    library's discrete adjoint (checkpointed recomputation).
+
+    The solver keeps one recorded run: a backward pass raises if the solver
+    recorded another run (or had its porous fields replaced) after the
+    forward pass it belongs to, instead of returning that run's gradient."""
     import torch
 
     class _MeltingRun(torch.autograd.Function):
@@ -463,11 +473,17 @@ def melting_run(solver, logK, eps, steps):
             solver.set_porous(ep.detach().float().cpu().numpy(), K)
             solver.reset()
             solver.record(steps)
+            ctx.record_id = solver.record_id
             F = solver.fields_device()
             return F["T"].to(lk.device), F["fl"].to(lk.device)
 
         @staticmethod
         def backward(ctx, dT, dfl):
+            if solver.record_id != ctx.record_id:
+                raise RuntimeError(
+                    "melting_run: the solver recorded another run after this one's forward "
+                    "pass; call backward before the next melting_run on the same solver, or "
+                    "use one solver per differentiated run")
             dev = dT.device if dT is not None else dfl.device
             z = torch.zeros((solver.ny, solver.nx), dtype=torch.float32, device="cuda")
             gT = z if dT is None else dT.to("cuda")

@@ -100,16 +100,6 @@ def gallium_cavity(n=200, steps=0):
                      **{"lambda": 0.2719})
 
 
-def gallium_fourier_steps(case, fo):
-    """Time steps for Fourier number fo = t alpha_l / H^2 of a
-    gallium_cavity case (alpha_l from Ra, Pr, Ma and H as in Sec. 4.3)."""
-    H, Ra, Pr = case["H"], case["Ra"], case["Pr"]
-    Ma, J = case["opts"]["Ma"], case["opts"]["J"]
-    tau_nu = 0.5 + Ma * J * H * math.sqrt(3.0 * Pr) / math.sqrt(Ra)
-    alpha_l = (tau_nu - 0.5) / 3.0 / J / Pr
-    return int(round(fo * H * H / alpha_l))
-
-
 CAVITY_BATCH_OPTS = dict(T_init=0.0, T_s=THETA_M_CAVITY - 0.02, T_l=THETA_M_CAVITY + 0.02,
                          convective=1)
 

@@ -8,6 +8,10 @@ nothing here comes from the HIP path.
   cavity_1024_2000.npz   Sec. 4.3 setting at 1024x1024 (Ra 1e6, Da 1e-4, seed 3),
                          2000 steps: T, u, f_l on the melted strip next to the
                          hot wall and on sampled rows.
+  cavity_1024_2000_diag.npz  the same run's whole-lattice reductions (the
+                         quantities dmrt_diag reports: sums of rho over liquid
+                         nodes, of sigma T + phi f_l / St, f_l and T, max |u|,
+                         the liquid count and the row fronts).
   cavity_1024_long.npz   the same workload over its full 100000 steps, with
                          snapshots after 20000, 50000 and 100000 steps.
   batch_512_smallest.npz the three smallest cavities of the 512-cavity batch
@@ -17,7 +21,7 @@ nothing here comes from the HIP path.
                          gallium in glass beads): T, u, f_l in full at Fourier
                          numbers 0.457 and 1.829 (209368 and 837931 steps).
 
-Usage: python tests/golden/make_golden.py [corner|cavity|cavity_long|batch|gallium ...]
+Usage: python tests/golden/make_golden.py [corner|cavity|cavity_diag|cavity_long|batch|gallium ...]
 """
 import os
 import sys
@@ -94,6 +98,20 @@ def cavity():
                         front=front_rows(F["fl"]))
 
 
+def cavity_diag():
+    case = W.cavity(nx=1024, ny=1024, steps=2000)
+    F = run(case, 2000)
+    liq = F["fl"] > 0
+    fr = front_rows(F["fl"])
+    eps, St = case["eps"].astype(np.float64), case["Ste"]
+    np.savez_compressed(os.path.join(HERE, "cavity_1024_2000_diag.npz"), steps=2000,
+                        mass=F["rho"][liq].sum(),
+                        enthalpy=(F["T"] + eps * F["fl"] / St).sum(),  # sigma = 1
+                        liquid=F["fl"].sum(), T_sum=F["T"].sum(), T_abs=np.abs(F["T"]).sum(),
+                        u_max=np.sqrt(F["ux"] ** 2 + F["uy"] ** 2).max(), active=liq.sum(),
+                        front_mean=fr.mean(), front_max=fr.max())
+
+
 LONG_SNAPS = (20000, 50000, 100000)
 LONG_STRIP = 192
 
@@ -136,7 +154,8 @@ GALLIUM_FO = (0.457, 1.829)
 def gallium():
     case = W.gallium_cavity()
     o = make_oracle(case, threads=int(os.environ.get("ORACLE_THREADS", "0")) or None)
-    steps = [W.gallium_fourier_steps(case, fo) for fo in GALLIUM_FO]
+    alpha_l = o.derived["alpha_l"]  # Sec. 4.3 mapping, through the oracle
+    steps = [int(round(fo * case["H"] ** 2 / alpha_l)) for fo in GALLIUM_FO]
     out = dict(fo=np.array(GALLIUM_FO), steps=np.array(steps))
     t = time.time()
     for k, n in enumerate(steps):

@@ -193,3 +193,28 @@ def test_adjoint_full_size_inverse_problem():
     _say("inverse problem: |g| %.6e, max|v| %.3f, central differences along g %s"
          % (float(g.norm()), float(v.abs().max()), fds))
     assert abs(fds[-1] - float(g.norm())) <= 5e-2 * float(g.norm())
+
+
+def test_backward_refuses_a_replaced_recording():
+    """Two differentiable runs on one solver before the first backward: the
+    first backward raises (its recording was replaced), the second run's
+    backward still gives the library's gradients."""
+    import torch
+    from paper_1503_08406_amd.dmrt import Solver, melting_run
+    case, steps, wT, wf = _case("convection")
+    s = Solver(case, fl_tol=1e-7)
+    lk = torch.tensor(np.log(case["K"].astype(np.float64)), dtype=torch.float32,
+                      device="cuda").requires_grad_(True)
+    ep = torch.tensor(case["eps"], dtype=torch.float32, device="cuda").requires_grad_(True)
+    wT_t = torch.tensor(wT, device="cuda")
+    wf_t = torch.tensor(wf, device="cuda")
+    T1, f1 = melting_run(s, lk, ep, steps)
+    T2, f2 = melting_run(s, lk * 1.01, ep, steps)
+    with pytest.raises(RuntimeError, match="recorded another run"):
+        ((T1 * wT_t).sum() + (f1 * wf_t).sum()).backward()
+    lk.grad = None
+    ep.grad = None
+    ((T2 * wT_t).sum() + (f2 * wf_t).sum()).backward()
+    gk, ge = s.adjoint(wT, wf)
+    assert np.array_equal(ep.grad.cpu().numpy(), ge)
+    s.close()

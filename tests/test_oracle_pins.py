@@ -886,3 +886,162 @@ def test_porous_layer_heated_from_below_onset(oracle_mod, phi):
 
     assert mode_rate(0.9 * 4 * math.pi ** 2) < -5e-5
     assert mode_rate(1.25 * 4 * math.pi ** 2) > 5e-5
+
+
+# ------------------------------------------- moving interface, pressure level
+SLAB_FLOW = dict(nx=96, K=4.0, nu=0.05, Ma=0.1, phi=0.5, Ste=1.0, T_i=-0.05, dT=0.01,
+                 times=(20000, 21000, 22000, 23000, 24000))
+
+
+def slab_flow_case(Ra_on=True, **over):
+    """Sec. 4.1 slab (hot wall theta = 1 at x-, adiabatic x+, periodic in y,
+    one node tall) melting into a porous solid just below its solidus, with
+    buoyancy along y, i.e. parallel to the front.  Lattice viscosity nu and
+    permeability K are fixed through Ra and Da (Sec. 4.3 mapping, H = nx)."""
+    p = dict(SLAB_FLOW)
+    p.update(over)
+    nx, H = p["nx"], float(p["nx"])
+    Ra = (p["Ma"] * H * math.sqrt(3.0) / (3 * p["nu"])) ** 2 if Ra_on else 0.0
+    return W.make_case("slab_flow", nx, 1, [1, 2, 0, 0], [1.0, 0, 0, 0], Ra=Ra,
+                       Da=p["K"] / H ** 2, Pr=1.0, Ste=p["Ste"], eps=p["phi"], H=H,
+                       T_init=p["T_i"], T_s=-p["dT"], T_l=p["dT"], T0=0.0, convective=1,
+                       Ma=p["Ma"], alpha_l=p["nu"]), p
+
+
+def brinkman_profile(x, T, fl, d, phi, Feps, x_wall):
+    """Quasi-steady Eq. (2) for a flow u_y(x) parallel to the walls:
+    nu_e u'' - (varphi nu_l / K_e) u - (varphi C_e / sqrt(K_e)) |u| u
+    + varphi g beta (T - T0) = 0 with varphi = phi f_l, K_e and C_e of Eq. (6)
+    in varphi (node values of T and f_l interpolated linearly), no slip at the
+    ghost wall x = -1 and at x = x_wall.  Solved independently of the lattice
+    (collocation, scipy)."""
+    from scipy.integrate import solve_bvp
+    K, nu_l, nu_e, gb = d["K_default"], d["nu_l"], d["nu_e"], d["gbeta"]
+
+    def rhs(s, y):
+        f = np.maximum(np.interp(s, x, fl), 1e-12)
+        vphi = phi * f
+        Ke = K * f ** 3 * ((1 - phi) / (1 - vphi)) ** 2
+        Ce = Feps * f ** -1.5
+        drag = (vphi * nu_l / Ke) * y[0] + (vphi * Ce / np.sqrt(Ke)) * np.abs(y[0]) * y[0]
+        return np.vstack([y[1], (drag - vphi * gb * np.interp(s, x, T)) / nu_e])
+
+    s = np.linspace(-1.0, x_wall, 1600)
+    sol = solve_bvp(rhs, lambda a, b: np.array([a[0], b[0]]), s, np.zeros((2, s.size)),
+                    tol=1e-10, max_nodes=400000)
+    assert sol.success
+    return sol.sol
+
+
+def check_slab_flow_follows_brinkman():
+    """Sec. 4 first paragraph (the moving solid-liquid interface is a no-slip
+    wall, Eq. 29 at solid sources; melted nodes join the flow) with Eqs. (2),
+    (4)-(6): in the melting slab with buoyancy parallel to the front the flow
+    is u = (0, u_y(x)), so u . grad T = 0 and T is exactly the conduction
+    solution, while u_y follows the quasi-steady Brinkman-Forchheimer balance
+    between the hot wall and the moving front (no slip at the centre of the
+    first solid node, as for a stationary solid wall).  The nodes near the
+    front are compared at 5e-3 of max u_y (the quasi-steady lag of a front
+    moving one node per ~1000 steps); the whole strip, including the
+    hot-wall Brinkman layer of ~3 nodes resolved by the second-order wall
+    extrapolation, at 4e-2."""
+    case, p = slab_flow_case()
+    cond, _ = slab_flow_case(Ra_on=False)
+    o, oc = oracle_from_case(case, nthreads=1), oracle_from_case(cond, nthreads=1)
+    d = o.derived
+    assert abs(d["alpha_l"] - oc.derived["alpha_l"]) < 1e-15
+    phi = p["phi"]
+    Feps = 1.75 / math.sqrt(175 * phi ** 3)  # Eq. (6)
+    x = np.arange(p["nx"])
+    errs = []
+    for t in p["times"]:
+        o.step(t - o.time)
+        oc.step(t - oc.time)
+        F, Fc = o.fields(), oc.fields()
+        assert np.abs(F["T"] - Fc["T"]).max() < 1e-9 and np.array_equal(F["fl"] > 0, Fc["fl"] > 0)
+        assert np.abs(F["ux"]).max() < 1e-10
+        fl, uy, T = F["fl"][0], F["uy"][0], F["T"][0]
+        xs = int(np.argmax(fl == 0))  # first solid node
+        assert 40 < xs < p["nx"] - 20 and uy[xs:].max() == 0
+        ua = brinkman_profile(x, T, fl, d, phi, Feps, float(xs))(x[:xs])[0]
+        err = np.abs(uy[:xs] - ua) / np.abs(ua).max()
+        errs.append((err[xs // 2:].max(), err.max()))
+        assert err[xs // 2:].max() < 5e-3, (t, err[xs // 2:].max())
+        assert err.max() < 4e-2, (t, err.max())
+    return errs
+
+
+def test_slab_flow_parallel_to_moving_front_follows_brinkman():
+    check_slab_flow_follows_brinkman()
+
+
+def gauge_case():
+    """A convecting porous cavity (hot left, cold right, adiabatic top and
+    bottom; log-normal K) whose left third is liquid and melts into the rest
+    during the run."""
+    nx, ny = 28, 20
+    rng = np.random.default_rng(7)
+    K = 5e-3 * 64 * 64 * np.exp(0.3 * rng.standard_normal((ny, nx)))
+    c = W.make_case("gauge", nx, ny, [1, 1, 2, 2], [1.0, 0.0, 0, 0], Ra=5e4, Da=5e-3, Pr=1,
+                    Ste=1, eps=0.5, K=K, H=64, T_init=0.3, T_s=0.38, T_l=0.42, convective=1)
+    T = np.full((ny, nx), 0.3)
+    T[:, :8] = 0.6
+    return c, T, (T > 0.5).astype(float)
+
+
+def gauge_state(w9, w5, T, fl, rho):
+    return w9[:, None, None] * rho * fl[None], w5[:, None, None] * T[None], fl
+
+
+def check_flow_independent_of_pressure_level(oracle_mod, steps=1500, drho=0.02):
+    """The model is incompressible (Sec. 3.1: rho0 in the force terms, the
+    pressure enters Eq. 2 through its gradient only), so the flow cannot
+    depend on the level of the pressure: the same melting, convecting cavity
+    started from a liquid at rest at density 1 and at 1 + drho must give the
+    same u, T and f_l, with the liquid's density shifted by exactly drho.
+    The scheme does this exactly when the extrapolation at walls and solid
+    nodes takes its equilibrium at the node's own density (Eq. 29 with
+    rho(x)) and a node that melts joins at its liquid neighbours' density;
+    a reference density rho0 in either place injects or removes mass at the
+    walls and the front."""
+    c, T, fl = gauge_case()
+    L = oracle_mod.lattice()
+    out = []
+    for rho in (1.0, 1.0 + drho):
+        o = oracle_from_case(c, nthreads=1)
+        o.set_state(*gauge_state(L["w9"], L["w5"], T, fl, rho))
+        o.step(steps)
+        out.append(o.fields())
+    A, B = out
+    liq = A["fl"] > 0
+    assert liq.sum() > fl.sum() + 30, "the front did not move"
+    umax = max(np.abs(A["ux"]).max(), np.abs(A["uy"]).max())
+    assert umax > 1e-4
+    du = max(np.abs(A["ux"] - B["ux"]).max(), np.abs(A["uy"] - B["uy"]).max())
+    assert du < 1e-11 * umax + 1e-15, du
+    assert np.abs(A["T"] - B["T"]).max() < 1e-12 and np.abs(A["fl"] - B["fl"]).max() < 1e-12
+    assert np.abs((B["rho"] - A["rho"])[liq] - drho).max() < 1e-13
+    return du / umax
+
+
+def test_flow_does_not_depend_on_the_pressure_level(oracle_mod):
+    check_flow_independent_of_pressure_level(oracle_mod)
+
+
+def test_closed_box_at_rest_keeps_any_density(oracle_mod):
+    """Without buoyancy a liquid at rest in a closed box (no-slip walls all
+    round, Sec. 4) stays at rest at whatever uniform density it has: mass is
+    conserved exactly and f_i = w_i rho."""
+    n, rho = 6, 1.013
+    c = W.make_case("box_rest", n, n + 1, [2, 2, 2, 2], [0] * 4, Ra=0, Da=1e-2, Pr=1, Ste=1,
+                    eps=0.6, T_init=0.5, T_s=0.1, T_l=0.2, convective=1)
+    o = oracle_from_case(c, nthreads=1)
+    w9, w5 = oracle_mod.lattice()["w9"], oracle_mod.lattice()["w5"]
+    f = np.broadcast_to(w9[:, None, None] * rho, (9, n + 1, n)).copy()
+    g = np.broadcast_to(w5[:, None, None] * 0.5, (5, n + 1, n)).copy()
+    o.set_state(f, g, np.ones((n + 1, n)))
+    o.step(500)
+    fs, _, _ = o.get_state()
+    np.testing.assert_allclose(fs, f, atol=1e-15)
+    F = o.fields()
+    assert np.abs(F["ux"]).max() < 1e-16 and np.abs(F["uy"]).max() < 1e-16
