@@ -486,8 +486,10 @@ struct orc_sim {
     int nx, ny;
     long nc, t;
     double *eps, *K, *Feps;
+    int feps_given;                   /* 0: F_eps follows eps through Eq. (6) */
     double *f, *g, *fl;               /* state: f[c*9+i], g[c*5+i], fl[c] */
     double *fpost, *gpost, *fnew, *gnew, *flnew;
+    double *gstr;                     /* streamed g before the latent source */
     double *T, *ux, *uy, *rho, *Fx, *Fy;
     unsigned char *chi;
     int *iters;
@@ -526,6 +528,7 @@ orc_sim *orc_create(const orc_params *p, const double *eps, const double *K,
     s->fnew = dalloc(nc * Q9);
     s->gnew = dalloc(nc * Q5);
     s->flnew = dalloc(nc);
+    s->gstr = dalloc(nc * Q5);
     s->T = dalloc(nc);
     s->ux = dalloc(nc);
     s->uy = dalloc(nc);
@@ -534,6 +537,7 @@ orc_sim *orc_create(const orc_params *p, const double *eps, const double *K,
     s->Fy = dalloc(nc);
     s->chi = (unsigned char *)calloc((size_t)nc, 1);
     s->iters = (int *)calloc((size_t)nc, sizeof(int));
+    s->feps_given = Feps != NULL;
     for (long c = 0; c < nc; ++c) {
         s->eps[c] = eps[c];
         s->K[c] = K ? K[c] : d.K_default;
@@ -557,7 +561,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     free(s->eps); free(s->K); free(s->Feps);
     free(s->f); free(s->g); free(s->fl);
-    free(s->fpost); free(s->gpost); free(s->fnew); free(s->gnew); free(s->flnew);
+    free(s->fpost); free(s->gpost); free(s->fnew); free(s->gnew); free(s->flnew); free(s->gstr);
     free(s->T); free(s->ux); free(s->uy); free(s->rho); free(s->Fx); free(s->Fy);
     free(s->chi); free(s->iters);
     free(s);
@@ -805,7 +809,10 @@ static void latent_r2(orc_sim *s)
     free(Ts);
 }
 
-static void one_step(orc_sim *s)
+/* One time step from the state (f, g, fl) into (fnew, gnew, flnew), keeping
+ * the intermediate fields (macros, post-collision populations, streamed g)
+ * in the simulation's work arrays. */
+static void compute_step(orc_sim *s)
 {
     const orc_params *p = &s->p;
     const int nx = s->nx, ny = s->ny;
@@ -864,6 +871,8 @@ static void one_step(orc_sim *s)
         }
     }
 
+    memcpy(s->gstr, s->gnew, sizeof(double) * (size_t)nc * Q5);
+
     /* Step 6: iterated enthalpy method and the latent source N^-1 dt S~
      * (Eqs. 30, 38, 40-42). */
     if (p->latent_mode == 1)
@@ -901,6 +910,11 @@ static void one_step(orc_sim *s)
         }
     }
 
+}
+
+static void one_step(orc_sim *s)
+{
+    compute_step(s);
     double *tmp;
     tmp = s->f; s->f = s->fnew; s->fnew = tmp;
     tmp = s->g; s->g = s->gnew; s->gnew = tmp;
@@ -957,4 +971,672 @@ void orc_iter_stats(const orc_sim *s, long *max_it, long *sum_it)
     }
     *max_it = mx;
     *sum_it = sm;
+}
+
+/* ====================================================================== */
+/* Discrete derivatives of one time step (tangent-linear and reverse)      */
+/* ====================================================================== */
+/*
+ * The step above is differentiated as a map from the state (f, g, f_l) at
+ * time k and the per-cell parameters (ln K, eps) to the state at time k+1,
+ * line by line, in FP64.  Where the map is not smooth, the derivative is
+ * taken as follows:
+ *   - the enthalpy update (Eqs. 38, 40-42) at its converged fixed point: on
+ *     the mushy branch f = (T* + a f^k - T_s) / (T_l - T_s + a), a =
+ *     eps / (sigma St); zero where f_l is clamped to 0 or 1;
+ *   - the flow mask, the liquid/solid status of every pull source and the
+ *     branch of each cell (melted, solidified) are held fixed;
+ *   - |v| in Eq. (26) has the subgradient 0 at v = 0.
+ * The derivative needs sigma and tau_T independent of f_l (sigma_s ==
+ * sigma_l, alpha_ratio == 1) and the default thermal model (R1, no
+ * variants); other settings are refused.
+ * F_eps follows eps through Eq. (6) unless it was given per cell.
+ * Vectors are in the simulation's internal layout (f[c*9+i], g[c*5+i]).
+ */
+
+/* Forward values of the velocity closure of one liquid cell, recomputed as
+ * macros_cell / orc_closure compute them. */
+typedef struct {
+    double fl, eps, phi, Ke, Ce, Gy, vx, vy, l0, l1, vm, R, den, ux, uy, um, A, B;
+    int nodrag;
+} clos_fw;
+
+static void closure_forward(const orc_sim *s, long c, double T, double jx, double jy, clos_fw *w)
+{
+    w->fl = s->fl[c];
+    w->eps = s->eps[c];
+    w->phi = w->eps * w->fl;
+    porous_at(w->eps, s->K[c], s->Feps[c], w->fl, &w->Ke, &w->Ce);
+    w->nodrag = !(w->eps < 1.0);
+    w->Gy = s->d.gbeta * (T - s->p.T0);
+    w->vx = jx;
+    w->vy = jy + 0.5 * w->phi * w->Gy;
+    if (w->nodrag) {
+        w->l0 = 0.5;
+        w->l1 = 0.0;
+        w->den = 1.0;
+    } else {
+        w->l0 = 0.5 * (1.0 + 0.5 * w->phi * s->d.nu_l / w->Ke);
+        w->l1 = 0.5 * w->phi * w->Ce / sqrt(w->Ke);
+    }
+    w->vm = sqrt(w->vx * w->vx + w->vy * w->vy);
+    w->R = sqrt(w->l0 * w->l0 + w->l1 * w->vm);
+    if (!w->nodrag) w->den = w->l0 + w->R;
+    w->ux = w->vx / w->den;
+    w->uy = w->vy / w->den;
+    w->um = sqrt(w->ux * w->ux + w->uy * w->uy);
+    w->A = w->nodrag ? 0.0 : w->phi * s->d.nu_l / w->Ke;
+    w->B = w->nodrag ? 0.0 : w->phi * w->Ce / sqrt(w->Ke);
+}
+
+/* Tangent of Eqs. (4)-(6), (26)-(28): from the tangents of jx, jy, T, f_l,
+ * eps and ln K to those of u, F and varphi. */
+static void closure_tl(const orc_sim *s, const clos_fw *w, double djx, double djy, double dT,
+                       double dfl, double deps, double dlnK, double *dux, double *duy,
+                       double *dFx, double *dFy, double *dphi)
+{
+    const double nu = s->d.nu_l, gb = s->d.gbeta;
+    const double ph = w->eps * dfl + deps * w->fl;
+    const double dGy = gb * dT;
+    const double dvx = djx;
+    const double dvy = djy + 0.5 * (ph * w->Gy + w->phi * dGy);
+    *dphi = ph;
+    if (w->nodrag) {
+        *dux = dvx;
+        *duy = dvy;
+        *dFx = 0.0;
+        *dFy = ph * w->Gy + w->phi * dGy;
+        return;
+    }
+    const double dlnFe = s->feps_given ? 0.0 : -1.5 * deps / w->eps; /* Eq. (6) */
+    const double dlnKe = dlnK + 3.0 * dfl / w->fl - 2.0 * deps / (1.0 - w->eps) +
+                         2.0 * ph / (1.0 - w->phi);
+    const double dlnCe = dlnFe - 1.5 * dfl / w->fl;
+    const double q = 0.25 * nu * w->phi / w->Ke;
+    const double dl0 = q * (ph / w->phi - dlnKe);
+    const double dl1 = w->l1 * (ph / w->phi + dlnCe - 0.5 * dlnKe);
+    const double dvm = w->vm > 0 ? (w->vx * dvx + w->vy * dvy) / w->vm : 0.0;
+    const double dR = (2.0 * w->l0 * dl0 + dl1 * w->vm + w->l1 * dvm) / (2.0 * w->R);
+    const double dden = dl0 + dR;
+    const double ux_d = (dvx - w->ux * dden) / w->den;
+    const double uy_d = (dvy - w->uy * dden) / w->den;
+    const double dum = w->um > 0 ? (w->ux * ux_d + w->uy * uy_d) / w->um : 0.0;
+    const double dA = w->A * (ph / w->phi - dlnKe);
+    const double dB = w->B * (ph / w->phi + dlnCe - 0.5 * dlnKe);
+    *dux = ux_d;
+    *duy = uy_d;
+    *dFx = -dA * w->ux - w->A * ux_d - dB * w->um * w->ux - w->B * dum * w->ux -
+           w->B * w->um * ux_d;
+    *dFy = -dA * w->uy - w->A * uy_d - dB * w->um * w->uy - w->B * dum * w->uy -
+           w->B * w->um * uy_d + ph * w->Gy + w->phi * dGy;
+}
+
+/* Reverse of closure_tl: adjoints of u, F and varphi in, adjoints of jx, jy,
+ * T, f_l, eps and ln K added to the outputs. */
+static void closure_ad(const orc_sim *s, const clos_fw *w, double bux, double buy, double bFx,
+                       double bFy, double bphi, double *bjx, double *bjy, double *bT,
+                       double *bfl, double *beps, double *blnK)
+{
+    const double nu = s->d.nu_l, gb = s->d.gbeta;
+    double bGy = 0.0, bvx = 0.0, bvy = 0.0;
+    if (w->nodrag) {
+        bphi += w->Gy * bFy;
+        bGy += w->phi * bFy;
+        bvx = bux;
+        bvy = buy;
+    } else {
+        double bA = 0, bB = 0, bum = 0, blnKe = 0, blnCe = 0, bden = 0, bl0 = 0, bl1 = 0;
+        double bR = 0, bvm = 0;
+        /* F */
+        bA += -w->ux * bFx - w->uy * bFy;
+        bB += -w->um * w->ux * bFx - w->um * w->uy * bFy;
+        bum += -w->B * w->ux * bFx - w->B * w->uy * bFy;
+        bux += (-w->A - w->B * w->um) * bFx;
+        buy += (-w->A - w->B * w->um) * bFy;
+        bphi += w->Gy * bFy;
+        bGy += w->phi * bFy;
+        /* B, A */
+        bphi += w->B / w->phi * bB + w->A / w->phi * bA;
+        blnCe += w->B * bB;
+        blnKe += -0.5 * w->B * bB - w->A * bA;
+        /* |u| */
+        if (w->um > 0) {
+            bux += w->ux / w->um * bum;
+            buy += w->uy / w->um * bum;
+        }
+        /* u = v / den */
+        bvx += bux / w->den;
+        bvy += buy / w->den;
+        bden += -(w->ux * bux + w->uy * buy) / w->den;
+        bl0 += bden;
+        bR += bden;
+        bl0 += w->l0 / w->R * bR;
+        bl1 += w->vm / (2.0 * w->R) * bR;
+        bvm += w->l1 / (2.0 * w->R) * bR;
+        if (w->vm > 0) {
+            bvx += w->vx / w->vm * bvm;
+            bvy += w->vy / w->vm * bvm;
+        }
+        /* l1, l0 */
+        bphi += w->l1 / w->phi * bl1;
+        blnCe += w->l1 * bl1;
+        blnKe += -0.5 * w->l1 * bl1;
+        const double q = 0.25 * nu * w->phi / w->Ke;
+        bphi += q / w->phi * bl0;
+        blnKe += -q * bl0;
+        /* ln C_e, ln K_e */
+        *bfl += -1.5 / w->fl * blnCe;
+        if (!s->feps_given) *beps += -1.5 / w->eps * blnCe;
+        *blnK += blnKe;
+        *bfl += 3.0 / w->fl * blnKe;
+        *beps += -2.0 / (1.0 - w->eps) * blnKe;
+        bphi += 2.0 / (1.0 - w->phi) * blnKe;
+    }
+    /* v */
+    *bjx += bvx;
+    *bjy += bvy;
+    bphi += 0.5 * w->Gy * bvy;
+    bGy += 0.5 * w->phi * bvy;
+    *bT += gb * bGy;
+    *beps += w->fl * bphi;
+    *bfl += w->eps * bphi;
+}
+
+/* Rates of Eq. (23). */
+static void rates9(const orc_sim *s, double *sv)
+{
+    const orc_params *p = &s->p;
+    double r[Q9] = {1, p->s_e, p->s_eps, 1, p->s_q, 1, p->s_q, 1.0 / s->d.tau_nu,
+                    1.0 / s->d.tau_nu};
+    memcpy(sv, r, sizeof r);
+}
+
+/* Tangent of the D2Q9 collision (Eqs. 19, 20, 22) of one liquid cell. */
+static void collide_f_tl(const orc_sim *s, const double *df, double drho, double ux, double uy,
+                         double Fx, double Fy, double phi, double dux, double duy, double dFx,
+                         double dFy, double dphi, double *dfp)
+{
+    double sv[Q9], dm[Q9], dmeq[Q9], dS[Q9], dmp[Q9];
+    rates9(s, sv);
+    for (int a = 0; a < Q9; ++a) {
+        double v = 0;
+        for (int i = 0; i < Q9; ++i) v += s->L9.M[a][i] * df[i];
+        dm[a] = v;
+    }
+    const double q = (ux * ux + uy * uy) / phi;
+    const double dq = (2 * ux * dux + 2 * uy * duy) / phi - q * dphi / phi;
+    const double m7 = (ux * ux - uy * uy) / phi, m8 = ux * uy / phi;
+    dmeq[0] = drho;
+    dmeq[1] = -2 * drho + 3 * dq;
+    dmeq[2] = drho - 3 * dq;
+    dmeq[3] = dux;
+    dmeq[4] = -dux;
+    dmeq[5] = duy;
+    dmeq[6] = -duy;
+    dmeq[7] = (2 * ux * dux - 2 * uy * duy) / phi - m7 * dphi / phi;
+    dmeq[8] = (dux * uy + ux * duy) / phi - m8 * dphi / phi;
+    const double uF = ux * Fx + uy * Fy;
+    const double duF = dux * Fx + ux * dFx + duy * Fy + uy * dFy;
+    const double S1 = 6 * uF / phi, S7 = 2 * (ux * Fx - uy * Fy) / phi,
+                 S8 = (ux * Fy + uy * Fx) / phi;
+    dS[0] = 0;
+    dS[1] = 6 * duF / phi - S1 * dphi / phi;
+    dS[2] = -dS[1];
+    dS[3] = dFx;
+    dS[4] = -dFx;
+    dS[5] = dFy;
+    dS[6] = -dFy;
+    dS[7] = 2 * (dux * Fx + ux * dFx - duy * Fy - uy * dFy) / phi - S7 * dphi / phi;
+    dS[8] = (dux * Fy + ux * dFy + duy * Fx + uy * dFx) / phi - S8 * dphi / phi;
+    for (int a = 0; a < Q9; ++a)
+        dmp[a] = dm[a] - sv[a] * (dm[a] - dmeq[a]) + DT * (1.0 - sv[a] / 2.0) * dS[a];
+    for (int i = 0; i < Q9; ++i) {
+        double v = 0;
+        for (int a = 0; a < Q9; ++a) v += s->L9.Minv[i][a] * dmp[a];
+        dfp[i] = v;
+    }
+}
+
+/* Reverse of collide_f_tl: adjoint of f+ in; adjoints of f, rho, u, F and
+ * varphi added to the outputs. */
+static void collide_f_ad(const orc_sim *s, const double *bfp, double ux, double uy, double Fx,
+                         double Fy, double phi, double *bf, double *brho, double *bux,
+                         double *buy, double *bFx, double *bFy, double *bphi)
+{
+    double sv[Q9], bmp[Q9], bm[Q9], bmeq[Q9], bS[Q9];
+    rates9(s, sv);
+    for (int a = 0; a < Q9; ++a) {
+        double v = 0;
+        for (int i = 0; i < Q9; ++i) v += s->L9.Minv[i][a] * bfp[i];
+        bmp[a] = v;
+    }
+    for (int a = 0; a < Q9; ++a) {
+        bm[a] = (1.0 - sv[a]) * bmp[a];
+        bmeq[a] = sv[a] * bmp[a];
+        bS[a] = DT * (1.0 - sv[a] / 2.0) * bmp[a];
+    }
+    for (int i = 0; i < Q9; ++i) {
+        double v = 0;
+        for (int a = 0; a < Q9; ++a) v += s->L9.M[a][i] * bm[a];
+        bf[i] += v;
+    }
+    const double q = (ux * ux + uy * uy) / phi;
+    const double m7 = (ux * ux - uy * uy) / phi, m8 = ux * uy / phi;
+    *brho += bmeq[0] - 2 * bmeq[1] + bmeq[2];
+    const double bq = 3 * bmeq[1] - 3 * bmeq[2];
+    *bux += 2 * ux / phi * bq + bmeq[3] - bmeq[4] + 2 * ux / phi * bmeq[7] + uy / phi * bmeq[8];
+    *buy += 2 * uy / phi * bq + bmeq[5] - bmeq[6] - 2 * uy / phi * bmeq[7] + ux / phi * bmeq[8];
+    *bphi += -q / phi * bq - m7 / phi * bmeq[7] - m8 / phi * bmeq[8];
+    const double uF = ux * Fx + uy * Fy;
+    const double S1 = 6 * uF / phi, S7 = 2 * (ux * Fx - uy * Fy) / phi,
+                 S8 = (ux * Fy + uy * Fx) / phi;
+    const double b1 = bS[1] - bS[2];
+    const double buF = 6 / phi * b1;
+    *bphi += -S1 / phi * b1 - S7 / phi * bS[7] - S8 / phi * bS[8];
+    *bFx += bS[3] - bS[4];
+    *bFy += bS[5] - bS[6];
+    *bux += 2 / phi * Fx * bS[7] + Fy / phi * bS[8] + Fx * buF;
+    *bFx += 2 / phi * ux * bS[7] + uy / phi * bS[8] + ux * buF;
+    *buy += -2 / phi * Fy * bS[7] + Fx / phi * bS[8] + Fy * buF;
+    *bFy += -2 / phi * uy * bS[7] + ux / phi * bS[8] + uy * buF;
+}
+
+/* Tangent of the D2Q5 collision (Eqs. 34, 35, 37) with uniform sigma, tau_T. */
+static void collide_g_tl(const orc_sim *s, long c, const double *dg, double dT, double T,
+                         double ux, double uy, double dux, double duy, double *dgp)
+{
+    const orc_params *p = &s->p;
+    const double sig = p->sigma_s, th = p->convective ? 1.0 : 0.0;
+    const double za = 1.0 / tauT_of(p, &s->d, s->eps[c], s->fl[c]);
+    const double theta[Q5] = {1, za, za, p->zeta_e, p->zeta_nu};
+    double dn[Q5], dneq[Q5], dnp[Q5];
+    for (int a = 0; a < Q5; ++a) {
+        double v = 0;
+        for (int i = 0; i < Q5; ++i) v += s->L5.N[a][i] * dg[i];
+        dn[a] = v;
+    }
+    dneq[0] = dT;
+    dneq[1] = th * (dux * T + ux * dT) / sig;
+    dneq[2] = th * (duy * T + uy * dT) / sig;
+    dneq[3] = p->varpi * dT;
+    dneq[4] = 0;
+    for (int a = 0; a < Q5; ++a) dnp[a] = dn[a] - theta[a] * (dn[a] - dneq[a]);
+    for (int i = 0; i < Q5; ++i) {
+        double v = 0;
+        for (int a = 0; a < Q5; ++a) v += s->L5.Ninv[i][a] * dnp[a];
+        dgp[i] = v;
+    }
+}
+
+static void collide_g_ad(const orc_sim *s, long c, const double *bgp, double T, double ux,
+                         double uy, double *bg, double *bT, double *bux, double *buy)
+{
+    const orc_params *p = &s->p;
+    const double sig = p->sigma_s, th = p->convective ? 1.0 : 0.0;
+    const double za = 1.0 / tauT_of(p, &s->d, s->eps[c], s->fl[c]);
+    const double theta[Q5] = {1, za, za, p->zeta_e, p->zeta_nu};
+    double bnp[Q5], bn[Q5], bneq[Q5];
+    for (int a = 0; a < Q5; ++a) {
+        double v = 0;
+        for (int i = 0; i < Q5; ++i) v += s->L5.Ninv[i][a] * bgp[i];
+        bnp[a] = v;
+        bn[a] = (1.0 - theta[a]) * bnp[a];
+        bneq[a] = theta[a] * bnp[a];
+    }
+    for (int i = 0; i < Q5; ++i) {
+        double v = 0;
+        for (int a = 0; a < Q5; ++a) v += s->L5.N[a][i] * bn[a];
+        bg[i] += v;
+    }
+    *bT += bneq[0] + p->varpi * bneq[3] + th * (ux * bneq[1] + uy * bneq[2]) / sig;
+    *bux += th * T / sig * bneq[1];
+    *buy += th * T / sig * bneq[2];
+}
+
+/* The latent weights w~ = N^-1 (1, 0, 0, varpi, 0) of add_latent. */
+static void latent_weights(const orc_sim *s, double *wt)
+{
+    for (int i = 0; i < Q5; ++i) wt[i] = s->L5.Ninv[i][0] + s->p.varpi * s->L5.Ninv[i][3];
+}
+
+static int adjoint_scope(const orc_sim *s)
+{
+    const orc_params *p = &s->p;
+    if (p->latent_mode != 0 || p->sigma_mode != 0 || p->ke_mode != 0) return -1;
+    if (p->sigma_s != p->sigma_l || p->alpha_ratio != 1.0) return -2;
+    return 0;
+}
+
+/* Tangent of one step at the current state, internal layout; NULL parameter
+ * tangents are zero. */
+static void step_tl(orc_sim *s, const double *df, const double *dg, const double *dfl,
+                    const double *dlnK, const double *deps, double *dfn, double *dgn,
+                    double *dfln)
+{
+    const orc_params *p = &s->p;
+    const int nx = s->nx, ny = s->ny;
+    const long nc = s->nc;
+    compute_step(s);
+    double *dT = dalloc(nc), *dux = dalloc(nc), *duy = dalloc(nc), *dphi = dalloc(nc);
+    double *drho = dalloc(nc), *dfp = dalloc(nc * Q9), *dgp = dalloc(nc * Q5);
+    double *dgs = dalloc(nc * Q5), *dfs = dalloc(nc * Q9);
+    for (long c = 0; c < nc; ++c) {
+        double t = 0;
+        for (int i = 0; i < Q5; ++i) t += dg[c * Q5 + i];
+        dT[c] = t;
+        if (s->chi[c]) {
+            double r = 0, jx = 0, jy = 0, djx = 0, djy = 0;
+            for (int i = 0; i < Q9; ++i) {
+                const double fi = s->f[c * Q9 + i], di = df[c * Q9 + i];
+                r += di;
+                jx += s->L9.ex[i] * fi;
+                jy += s->L9.ey[i] * fi;
+                djx += s->L9.ex[i] * di;
+                djy += s->L9.ey[i] * di;
+            }
+            drho[c] = r;
+            clos_fw w;
+            closure_forward(s, c, s->T[c], jx, jy, &w);
+            double dFx, dFy;
+            closure_tl(s, &w, djx, djy, t, dfl[c], deps ? deps[c] : 0.0, dlnK ? dlnK[c] : 0.0,
+                       &dux[c], &duy[c], &dFx, &dFy, &dphi[c]);
+            collide_f_tl(s, &df[c * Q9], drho[c], s->ux[c], s->uy[c], s->Fx[c], s->Fy[c],
+                         s->eps[c] * s->fl[c], dux[c], duy[c], dFx, dFy, dphi[c], &dfp[c * Q9]);
+        }
+        collide_g_tl(s, c, &dg[c * Q5], dT[c], s->T[c], s->ux[c], s->uy[c], dux[c], duy[c],
+                     &dgp[c * Q5]);
+    }
+    const double cu = 1.0 / (p->sigma_s * s->d.csT2);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const long c = (long)y * nx + x;
+            int sx, sy, side;
+            for (int i = 0; i < Q5; ++i) {
+                if (source_node(s, x, y, s->L5.ex[i], s->L5.ey[i], &sx, &sy, &side)) {
+                    dgs[c * Q5 + i] = dgp[((long)sy * nx + sx) * Q5 + i];
+                } else {
+                    const double w5 = s->L5.w[i];
+                    const double eu = s->L5.ex[i] * s->ux[c] + s->L5.ey[i] * s->uy[c];
+                    const double deu = s->L5.ex[i] * dux[c] + s->L5.ey[i] * duy[c];
+                    const double dTw = p->bc_kind[side] == ORC_WALL_T ? 0.0 : w5 * dT[c];
+                    dgs[c * Q5 + i] = dTw + dgp[c * Q5 + i] -
+                                      w5 * (dT[c] * (1.0 + eu * cu) + s->T[c] * deu * cu);
+                }
+            }
+            if (!s->chi[c]) continue;
+            const double ph = s->eps[c] * s->fl[c];
+            const double ux = s->ux[c], uy = s->uy[c], uu = ux * ux + uy * uy;
+            for (int i = 0; i < Q9; ++i) {
+                long sc;
+                if (source_node(s, x, y, s->L9.ex[i], s->L9.ey[i], &sx, &sy, &side) &&
+                    s->chi[sc = (long)sy * nx + sx]) {
+                    dfs[c * Q9 + i] = dfp[sc * Q9 + i];
+                } else {
+                    const double eu = s->L9.ex[i] * ux + s->L9.ey[i] * uy;
+                    const double deu = s->L9.ex[i] * dux[c] + s->L9.ey[i] * duy[c];
+                    const double duu = 2 * (ux * dux[c] + uy * duy[c]);
+                    dfs[c * Q9 + i] = dfp[c * Q9 + i] -
+                        s->L9.w[i] * (3 * deu + 9 * eu * deu / ph - 4.5 * eu * eu * dphi[c] / (ph * ph) -
+                                      1.5 * duu / ph + 1.5 * uu * dphi[c] / (ph * ph));
+                }
+            }
+        }
+    double wt[Q5];
+    latent_weights(s, wt);
+    const double dTm = p->T_l - p->T_s;
+    for (long c = 0; c < nc; ++c) {
+        double dTs = 0;
+        for (int i = 0; i < Q5; ++i) dTs += dgs[c * Q5 + i];
+        const double a = s->eps[c] / (p->sigma_s * p->Ste);
+        const double da = (deps ? deps[c] : 0.0) / (p->sigma_s * p->Ste);
+        const double fk = s->fl[c], fn = s->flnew[c];
+        const double d1 = (fn > 0 && fn < 1) ? (dTs + a * dfl[c] + (fk - fn) * da) / (dTm + a) : 0.0;
+        const double dS0 = -da * (fn - fk) - a * (d1 - dfl[c]);
+        for (int i = 0; i < Q5; ++i) dgn[c * Q5 + i] = dgs[c * Q5 + i] + DT * wt[i] * dS0;
+        dfln[c] = d1;
+    }
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const long c = (long)y * nx + x;
+            const int was = s->fl[c] > 0, now = s->flnew[c] > 0;
+            if (now && !was) {
+                double dsum = 0;
+                int cnt = 0;
+                for (int i = 1; i < Q9; ++i) {
+                    int sx, sy, side;
+                    if (source_node(s, x, y, s->L9.ex[i], s->L9.ey[i], &sx, &sy, &side)) {
+                        const long sc = (long)sy * nx + sx;
+                        if (s->chi[sc]) {
+                            dsum += drho[sc];
+                            ++cnt;
+                        }
+                    }
+                }
+                for (int i = 0; i < Q9; ++i) dfn[c * Q9 + i] = cnt ? s->L9.w[i] * dsum / cnt : 0.0;
+            } else if (!now) {
+                for (int i = 0; i < Q9; ++i) dfn[c * Q9 + i] = 0.0;
+            } else {
+                for (int i = 0; i < Q9; ++i) dfn[c * Q9 + i] = dfs[c * Q9 + i];
+            }
+        }
+    free(dT); free(dux); free(duy); free(dphi); free(drho); free(dfp); free(dgp); free(dgs);
+    free(dfs);
+}
+
+/* Reverse of step_tl at the current state: adjoints of the next state in,
+ * adjoints of the current state out, parameter adjoints added to blnK, beps. */
+static void step_ad(orc_sim *s, const double *bfn, const double *bgn, const double *bfln,
+                    double *bf, double *bg, double *bfl, double *blnK, double *beps)
+{
+    const orc_params *p = &s->p;
+    const int nx = s->nx, ny = s->ny;
+    const long nc = s->nc;
+    compute_step(s);
+    double *bT = dalloc(nc), *bux = dalloc(nc), *buy = dalloc(nc), *bphi = dalloc(nc);
+    double *brho = dalloc(nc), *bfp = dalloc(nc * Q9), *bgp = dalloc(nc * Q5);
+    double *bgs = dalloc(nc * Q5), *bfs = dalloc(nc * Q9);
+    memset(bf, 0, sizeof(double) * (size_t)nc * Q9);
+    memset(bg, 0, sizeof(double) * (size_t)nc * Q5);
+    memset(bfl, 0, sizeof(double) * (size_t)nc);
+    /* mask update */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const long c = (long)y * nx + x;
+            const int was = s->fl[c] > 0, now = s->flnew[c] > 0;
+            if (now && !was) {
+                double br = 0;
+                for (int i = 0; i < Q9; ++i) br += s->L9.w[i] * bfn[c * Q9 + i];
+                long nb[Q9];
+                int cnt = 0;
+                for (int i = 1; i < Q9; ++i) {
+                    int sx, sy, side;
+                    if (source_node(s, x, y, s->L9.ex[i], s->L9.ey[i], &sx, &sy, &side)) {
+                        const long sc = (long)sy * nx + sx;
+                        if (s->chi[sc]) nb[cnt++] = sc;
+                    }
+                }
+                for (int k = 0; k < cnt; ++k) brho[nb[k]] += br / cnt;
+            } else if (now) {
+                for (int i = 0; i < Q9; ++i) bfs[c * Q9 + i] = bfn[c * Q9 + i];
+            }
+        }
+    /* latent source and enthalpy fixed point */
+    double wt[Q5];
+    latent_weights(s, wt);
+    const double dTm = p->T_l - p->T_s;
+    for (long c = 0; c < nc; ++c) {
+        const double a = s->eps[c] / (p->sigma_s * p->Ste);
+        const double fk = s->fl[c], fn = s->flnew[c];
+        double bS0 = 0;
+        for (int i = 0; i < Q5; ++i) {
+            bgs[c * Q5 + i] = bgn[c * Q5 + i];
+            bS0 += DT * wt[i] * bgn[c * Q5 + i];
+        }
+        double ba = -(fn - fk) * bS0;
+        const double b1 = bfln[c] - a * bS0;
+        bfl[c] += a * bS0;
+        if (fn > 0 && fn < 1) {
+            const double bTs = b1 / (dTm + a);
+            bfl[c] += a * b1 / (dTm + a);
+            ba += (fk - fn) * b1 / (dTm + a);
+            for (int i = 0; i < Q5; ++i) bgs[c * Q5 + i] += bTs;
+        }
+        beps[c] += ba / (p->sigma_s * p->Ste);
+    }
+    /* streaming (adjoint of the gathers) */
+    const double cu = 1.0 / (p->sigma_s * s->d.csT2);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const long c = (long)y * nx + x;
+            int sx, sy, side;
+            for (int i = 0; i < Q5; ++i) {
+                const double b = bgs[c * Q5 + i];
+                if (source_node(s, x, y, s->L5.ex[i], s->L5.ey[i], &sx, &sy, &side)) {
+                    bgp[((long)sy * nx + sx) * Q5 + i] += b;
+                } else {
+                    const double w5 = s->L5.w[i];
+                    const double eu = s->L5.ex[i] * s->ux[c] + s->L5.ey[i] * s->uy[c];
+                    if (p->bc_kind[side] != ORC_WALL_T) bT[c] += w5 * b;
+                    bgp[c * Q5 + i] += b;
+                    bT[c] += -w5 * (1.0 + eu * cu) * b;
+                    bux[c] += -w5 * s->T[c] * cu * s->L5.ex[i] * b;
+                    buy[c] += -w5 * s->T[c] * cu * s->L5.ey[i] * b;
+                }
+            }
+            if (!s->chi[c]) continue;
+            const double ph = s->eps[c] * s->fl[c];
+            const double ux = s->ux[c], uy = s->uy[c], uu = ux * ux + uy * uy;
+            for (int i = 0; i < Q9; ++i) {
+                const double b = bfs[c * Q9 + i];
+                long sc;
+                if (source_node(s, x, y, s->L9.ex[i], s->L9.ey[i], &sx, &sy, &side) &&
+                    s->chi[sc = (long)sy * nx + sx]) {
+                    bfp[sc * Q9 + i] += b;
+                } else {
+                    const double wi = s->L9.w[i];
+                    const double eu = s->L9.ex[i] * ux + s->L9.ey[i] * uy;
+                    bfp[c * Q9 + i] += b;
+                    const double beu = -wi * (3 + 9 * eu / ph) * b;
+                    const double buu = wi * 1.5 / ph * b;
+                    bux[c] += s->L9.ex[i] * beu + 2 * ux * buu;
+                    buy[c] += s->L9.ey[i] * beu + 2 * uy * buu;
+                    bphi[c] += -wi * (-4.5 * eu * eu / (ph * ph) + 1.5 * uu / (ph * ph)) * b;
+                }
+            }
+        }
+    /* collisions and macros */
+    for (long c = 0; c < nc; ++c) {
+        collide_g_ad(s, c, &bgp[c * Q5], s->T[c], s->ux[c], s->uy[c], &bg[c * Q5], &bT[c],
+                     &bux[c], &buy[c]);
+        if (s->chi[c]) {
+            double bFx = 0, bFy = 0;
+            collide_f_ad(s, &bfp[c * Q9], s->ux[c], s->uy[c], s->Fx[c], s->Fy[c],
+                         s->eps[c] * s->fl[c], &bf[c * Q9], &brho[c], &bux[c], &buy[c], &bFx,
+                         &bFy, &bphi[c]);
+            double jx = 0, jy = 0;
+            for (int i = 0; i < Q9; ++i) {
+                jx += s->L9.ex[i] * s->f[c * Q9 + i];
+                jy += s->L9.ey[i] * s->f[c * Q9 + i];
+            }
+            clos_fw w;
+            closure_forward(s, c, s->T[c], jx, jy, &w);
+            double bjx = 0, bjy = 0;
+            closure_ad(s, &w, bux[c], buy[c], bFx, bFy, bphi[c], &bjx, &bjy, &bT[c], &bfl[c],
+                       &beps[c], &blnK[c]);
+            for (int i = 0; i < Q9; ++i)
+                bf[c * Q9 + i] += brho[c] + s->L9.ex[i] * bjx + s->L9.ey[i] * bjy;
+        }
+        for (int i = 0; i < Q5; ++i) bg[c * Q5 + i] += bT[c];
+    }
+    free(bT); free(bux); free(buy); free(bphi); free(brho); free(bfp); free(bgp); free(bgs);
+    free(bfs);
+}
+
+static void to_internal(const orc_sim *s, const double *src, double *dst, int q)
+{
+    for (long c = 0; c < s->nc; ++c)
+        for (int i = 0; i < q; ++i) dst[c * q + i] = src ? src[i * s->nc + c] : 0.0;
+}
+
+static void to_planar(const orc_sim *s, const double *src, double *dst, int q)
+{
+    for (long c = 0; c < s->nc; ++c)
+        for (int i = 0; i < q; ++i) dst[i * s->nc + c] = src[c * q + i];
+}
+
+int orc_step_tl(orc_sim *s, const double *df, const double *dg, const double *dfl,
+                const double *dlnK, const double *deps, double *dfn, double *dgn, double *dfln)
+{
+    if (adjoint_scope(s)) return -1;
+    const long nc = s->nc;
+    double *a = dalloc(nc * Q9), *b = dalloc(nc * Q5), *c = dalloc(nc);
+    double *ao = dalloc(nc * Q9), *bo = dalloc(nc * Q5);
+    to_internal(s, df, a, Q9);
+    to_internal(s, dg, b, Q5);
+    to_internal(s, dfl, c, 1);
+    step_tl(s, a, b, c, dlnK, deps, ao, bo, dfln);
+    to_planar(s, ao, dfn, Q9);
+    to_planar(s, bo, dgn, Q5);
+    free(a); free(b); free(c); free(ao); free(bo);
+    return 0;
+}
+
+int orc_step_ad(orc_sim *s, const double *bfn, const double *bgn, const double *bfln,
+                double *bf, double *bg, double *bfl, double *blnK, double *beps)
+{
+    if (adjoint_scope(s)) return -1;
+    const long nc = s->nc;
+    double *a = dalloc(nc * Q9), *b = dalloc(nc * Q5), *c = dalloc(nc);
+    double *ao = dalloc(nc * Q9), *bo = dalloc(nc * Q5);
+    to_internal(s, bfn, a, Q9);
+    to_internal(s, bgn, b, Q5);
+    to_internal(s, bfln, c, 1);
+    step_ad(s, a, b, c, ao, bo, bfl, blnK, beps);
+    to_planar(s, ao, bf, Q9);
+    to_planar(s, bo, bg, Q5);
+    free(a); free(b); free(c); free(ao); free(bo);
+    return 0;
+}
+
+int orc_adjoint_run(orc_sim *s, long n, const double *dL_dT, const double *dL_dfl,
+                    double *grad_lnK, double *grad_eps)
+{
+    if (adjoint_scope(s)) return -1;
+    if (n < 1) return -2;
+    const long nc = s->nc;
+    const size_t per = (size_t)nc * (Q9 + Q5 + 1);
+    if ((double)per * n * sizeof(double) > 4e9) return -3; /* keeps every state */
+    double *hist = (double *)malloc(per * (size_t)n * sizeof(double));
+    if (!hist) return -4;
+    const long t0 = s->t;
+    for (long k = 0; k < n; ++k) {
+        double *h = hist + per * (size_t)k;
+        memcpy(h, s->f, sizeof(double) * nc * Q9);
+        memcpy(h + nc * Q9, s->g, sizeof(double) * nc * Q5);
+        memcpy(h + nc * (Q9 + Q5), s->fl, sizeof(double) * nc);
+        one_step(s);
+    }
+    double *bfn = dalloc(nc * Q9), *bgn = dalloc(nc * Q5), *bfln = dalloc(nc);
+    double *bf = dalloc(nc * Q9), *bg = dalloc(nc * Q5), *bfl = dalloc(nc);
+    for (long c = 0; c < nc; ++c) {
+        for (int i = 0; i < Q5; ++i) bgn[c * Q5 + i] = dL_dT ? dL_dT[c] : 0.0; /* T = sum g */
+        bfln[c] = dL_dfl ? dL_dfl[c] : 0.0;
+        grad_lnK[c] = 0.0;
+        grad_eps[c] = 0.0;
+    }
+    for (long k = n - 1; k >= 0; --k) {
+        const double *h = hist + per * (size_t)k;
+        memcpy(s->f, h, sizeof(double) * nc * Q9);
+        memcpy(s->g, h + nc * Q9, sizeof(double) * nc * Q5);
+        memcpy(s->fl, h + nc * (Q9 + Q5), sizeof(double) * nc);
+        step_ad(s, bfn, bgn, bfln, bf, bg, bfl, grad_lnK, grad_eps);
+        double *t;
+        t = bfn; bfn = bf; bf = t;
+        t = bgn; bgn = bg; bg = t;
+        t = bfln; bfln = bfl; bfl = t;
+    }
+    /* the reverse sweep ended on the state of step 0, the initial state */
+    s->t = t0;
+    free(hist); free(bfn); free(bgn); free(bfln); free(bf); free(bg); free(bfl);
+    return 0;
 }

@@ -122,6 +122,28 @@ void orc_post_collision(const orc_sim *s, double *fpost, double *gpost);
 /* Enthalpy iteration counts of the last step: max and total. */
 void orc_iter_stats(const orc_sim *s, long *max_it, long *sum_it);
 
+/* ---- discrete derivatives of the step ----------------------------------- */
+/* The step is differentiated at its converged enthalpy fixed point (zero where
+ * f_l is clamped), with the flow mask and pull-source kinds held fixed and
+ * the subgradient 0 of |v| at v = 0.  They need sigma_s == sigma_l,
+ * alpha_ratio == 1 and the default thermal model; otherwise they return a
+ * negative value.  Planar layouts as orc_set_state; the state is not changed.
+ *
+ * Tangent of one step at the current state along (df, dg, dfl) and the
+ * per-cell parameter directions dlnK (of ln K) and deps (either may be NULL). */
+int orc_step_tl(orc_sim *s, const double *df, const double *dg, const double *dfl,
+                const double *dlnK, const double *deps, double *dfn, double *dgn, double *dfln);
+/* Transpose of orc_step_tl: adjoints of the next state in, adjoints of the
+ * current state out; the parameter adjoints are ADDED to blnK and beps. */
+int orc_step_ad(orc_sim *s, const double *bfn, const double *bgn, const double *bfln,
+                double *bf, double *bg, double *bfl, double *blnK, double *beps);
+/* Gradients of a loss of the fields after n steps from the current state
+ * (adjoints dL_dT, dL_dfl of T = sum g and f_l; either may be NULL) with
+ * respect to ln K and eps per cell.  Keeps every state of the run (refused
+ * beyond 4 GB); the state is left unchanged. */
+int orc_adjoint_run(orc_sim *s, long n, const double *dL_dT, const double *dL_dfl,
+                    double *grad_lnK, double *grad_eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,12 @@ def _load():
         lib.orc_fields.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP, _DP]
         lib.orc_post_collision.argtypes = [C.c_void_p, _DP, _DP]
         lib.orc_iter_stats.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long)]
+        lib.orc_step_tl.argtypes = [C.c_void_p] + [_DP] * 8
+        lib.orc_step_tl.restype = C.c_int
+        lib.orc_step_ad.argtypes = [C.c_void_p] + [_DP] * 8
+        lib.orc_step_ad.restype = C.c_int
+        lib.orc_adjoint_run.argtypes = [C.c_void_p, C.c_long, _DP, _DP, _DP, _DP]
+        lib.orc_adjoint_run.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -251,6 +257,45 @@ class OracleSim:
         fp = np.zeros((9, self.ny, self.nx)); gp = np.zeros((5, self.ny, self.nx))
         _load().orc_post_collision(self._h, _dp(fp), _dp(gp))
         return fp, gp
+
+    def _arr(self, a, q=0):
+        if a is None:
+            return None
+        shape = (q, self.ny, self.nx) if q else (self.ny, self.nx)
+        return np.ascontiguousarray(np.broadcast_to(a, shape), dtype=np.float64)
+
+    def step_tl(self, df, dg, dfl, dlnK=None, deps=None):
+        """Tangent of one step at the current state (planar arrays); returns
+        (dfn, dgn, dfln).  The state is not changed."""
+        a = [self._arr(df, 9), self._arr(dg, 5), self._arr(dfl), self._arr(dlnK), self._arr(deps)]
+        outs = [np.zeros((9, self.ny, self.nx)), np.zeros((5, self.ny, self.nx)),
+                np.zeros((self.ny, self.nx))]
+        rc = _load().orc_step_tl(self._h, *[None if x is None else _dp(x) for x in a],
+                                 *[_dp(x) for x in outs])
+        if rc != 0:
+            raise ValueError("orc_step_tl refused the model (%d)" % rc)
+        return tuple(outs)
+
+    def step_ad(self, bfn, bgn, bfln):
+        """Transpose of step_tl: (bf, bg, bfl, blnK, beps)."""
+        a = [self._arr(bfn, 9), self._arr(bgn, 5), self._arr(bfln)]
+        outs = [np.zeros((9, self.ny, self.nx)), np.zeros((5, self.ny, self.nx))] + \
+               [np.zeros((self.ny, self.nx)) for _ in range(3)]
+        rc = _load().orc_step_ad(self._h, *[_dp(x) for x in a], *[_dp(x) for x in outs])
+        if rc != 0:
+            raise ValueError("orc_step_ad refused the model (%d)" % rc)
+        return tuple(outs)
+
+    def adjoint_run(self, n, dL_dT=None, dL_dfl=None):
+        """Gradients (dL/dln K, dL/deps) of a loss of T and f_l after n steps
+        from the current state; the state is not changed."""
+        a = [self._arr(dL_dT), self._arr(dL_dfl)]
+        gk, ge = np.zeros((self.ny, self.nx)), np.zeros((self.ny, self.nx))
+        rc = _load().orc_adjoint_run(self._h, int(n), *[None if x is None else _dp(x) for x in a],
+                                     _dp(gk), _dp(ge))
+        if rc != 0:
+            raise ValueError("orc_adjoint_run failed (%d)" % rc)
+        return gk, ge
 
     def iter_stats(self):
         mx = C.c_long(); sm = C.c_long()
