@@ -188,6 +188,18 @@ int dmrt_get_populations(dmrt_t *h, float *fpost, float *gpost);
 /* Reductions of the current state (see dmrt_diag_t). */
 int dmrt_diag(dmrt_t *h, dmrt_diag_t *out);
 
+/* dmrt_diag for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reductions, with the same bits, computed without any allocation, in a fixed
+ * device scratch array of 4 MiB + 64 KiB that the library holds on each device
+ * it runs on (set up by dmrt_create) until the process ends.  A lattice needs
+ * 64 bytes per tile of 64 x 4 nodes plus 4 bytes per row (each rounded up to
+ * 256 bytes) plus 128 bytes: 4096 x 4096 needs 4.02 MiB and fits; a lattice
+ * that does not fit returns DMRT_ESIZE (dmrt_diag serves it).  Every call on a device shares that device's array:
+ * calls that overlap on one device (from any handle or thread) race, so the
+ * caller must serialise them.  Synchronises the handle's stream. */
+int dmrt_diag_noalloc(dmrt_t *h, dmrt_diag_t *out);
+
 /* Lattice constants the handle runs with. */
 int dmrt_get_derived(const dmrt_t *h, dmrt_derived *out);
 

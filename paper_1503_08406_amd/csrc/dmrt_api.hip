@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -46,6 +47,43 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
 }  // namespace
 
+// Device scratch of dmrt_diag_noalloc: the block partials of the diagnostics
+// (at most 65536 blocks of 8 doubles, 4 MiB), the row fronts and the ten
+// reduced results (64 KiB).  Each device the library runs on holds one copy
+// until the process ends; every call on that device shares it.
+constexpr size_t kScratchBytes = (size_t(4) << 20) + (size_t(64) << 10);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, found once per device
+// with that device current (the array's name is a host-side stand-in and
+// must not be passed to kernels).
+int scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(DMRT_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return DMRT_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(DMRT_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+    return DMRT_OK;
+}
+
+void* scratch_of(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+}
+
+}  // namespace
+
 struct dmrt {
     int dev = 0;
     hipStream_t stream = nullptr;
@@ -60,8 +98,8 @@ struct dmrt {
     char* base = nullptr;
     float *f[2]{}, *g[2]{}, *fl[2]{};
     float *ux = nullptr, *uy = nullptr, *eps = nullptr, *Ac = nullptr, *Bc = nullptr;
-    char* scratch = nullptr;
-    size_t scratch_bytes = 0;
+    char* work = nullptr;  // device work space of the field, population and diagnostics copies
+    size_t work_bytes = 0;
     int *it_sum = nullptr, *it_max = nullptr;
     hipGraphExec_t graph[2]{};
     double ergun_c = 175.0;
@@ -293,14 +331,14 @@ dmrtk::StepBufs bufs(dmrt* h, bool counted)
     return B;
 }
 
-int ensure_scratch(dmrt* h, size_t bytes)
+int ensure_work(dmrt* h, size_t bytes)
 {
-    if (h->scratch_bytes >= bytes) return DMRT_OK;
-    if (h->scratch) HIPCHK(hipFree(h->scratch));
-    h->scratch = nullptr;
-    h->scratch_bytes = 0;
-    HIPCHK(hipMalloc(&h->scratch, bytes));
-    h->scratch_bytes = bytes;
+    if (h->work_bytes >= bytes) return DMRT_OK;
+    if (h->work) HIPCHK(hipFree(h->work));
+    h->work = nullptr;
+    h->work_bytes = 0;
+    HIPCHK(hipMalloc(&h->work, bytes));
+    h->work_bytes = bytes;
     return DMRT_OK;
 }
 
@@ -358,10 +396,10 @@ int diag_impl(dmrt* h, dmrt_diag_t* out)
     const int nblk = dmrtk::tile_blocks(G, dmrtk::TY);
     const size_t pbytes = align256((size_t)nblk * dmrtk::DIAG_SLOTS * sizeof(double));
     const size_t fbytes = (size_t)G.ny * sizeof(float);
-    int rc = ensure_scratch(h, pbytes + align256(fbytes));
+    int rc = ensure_work(h, pbytes + align256(fbytes));
     if (rc) return rc;
-    double* part = (double*)h->scratch;
-    float* front = (float*)(h->scratch + pbytes);
+    double* part = (double*)h->work;
+    float* front = (float*)(h->work + pbytes);
     int nb = 0;
     const int a = h->cur;
     HIPCHK(dmrtk::launch_diag(G, h->P, h->f[a], h->g[a], h->fl[a], h->ux, h->uy, h->eps, h->flow,
@@ -631,6 +669,7 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     };
     hipError_t e = hipGetDevice(&h->dev);
     if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+    if ((rc = scratch_setup(h->dev))) return bail(rc);
 
     // Inputs: stage through host memory, validate, derive the drag coefficients.
     h->ergun_c = o.ergun_c;
@@ -702,9 +741,9 @@ int dmrt_set_state(dmrt_t* h, const float* f, const float* g, const float* fl)
     const size_t need = (f ? 9 : 0) * ncell + (g ? 5 : 0) * ncell + (fl ? 1 : 0) * ncell;
     float *df = nullptr, *dg = nullptr, *dfl = nullptr;
     if (need) {
-        int rc = ensure_scratch(h, need * sizeof(float));
+        int rc = ensure_work(h, need * sizeof(float));
         if (rc) return rc;
-        float* s = (float*)h->scratch;
+        float* s = (float*)h->work;
         if (f) { df = s; s += 9 * ncell; HIPCHK(hipMemcpyAsync(df, f, 9 * ncell * 4, hipMemcpyDefault, h->stream)); }
         if (g) { dg = s; s += 5 * ncell; HIPCHK(hipMemcpyAsync(dg, g, 5 * ncell * 4, hipMemcpyDefault, h->stream)); }
         if (fl) { dfl = s; HIPCHK(hipMemcpyAsync(dfl, fl, ncell * 4, hipMemcpyDefault, h->stream)); }
@@ -788,9 +827,9 @@ int dmrt_fields(dmrt_t* h, float* T, float* ux, float* uy, float* fl)
     HIPCHK(hipSetDevice(h->dev));
     const Geom& G = h->G;
     const size_t ncell = (size_t)G.nx * G.ny;
-    int rc = ensure_scratch(h, 4 * ncell * sizeof(float));
+    int rc = ensure_work(h, 4 * ncell * sizeof(float));
     if (rc) return rc;
-    float* s = (float*)h->scratch;
+    float* s = (float*)h->work;
     const int a = h->cur;
     HIPCHK(dmrtk::launch_fields(G, h->g[a], h->fl[a], h->ux, h->uy, h->flow, s, h->stream));
     float* dst[4] = {T, ux, uy, fl};
@@ -806,9 +845,9 @@ int dmrt_get_populations(dmrt_t* h, float* fpost, float* gpost)
     HIPCHK(hipSetDevice(h->dev));
     const Geom& G = h->G;
     const size_t ncell = (size_t)G.nx * G.ny;
-    int rc = ensure_scratch(h, 14 * ncell * sizeof(float));
+    int rc = ensure_work(h, 14 * ncell * sizeof(float));
     if (rc) return rc;
-    float* s = (float*)h->scratch;
+    float* s = (float*)h->work;
     const int a = h->cur;
     HIPCHK(dmrtk::launch_populations(G, h->f[a], h->g[a], h->fl[a], h->flow, s, s + 9 * ncell,
                                     h->stream));
@@ -823,6 +862,49 @@ int dmrt_diag(dmrt_t* h, dmrt_diag_t* out)
     if (!h || !out) return fail(DMRT_EINVAL, "null argument");
     HIPCHK(hipSetDevice(h->dev));
     return diag_impl(h, out);
+}
+
+int dmrt_diag_noalloc(dmrt_t* h, dmrt_diag_t* out)
+{
+    if (!h || !out) return fail(DMRT_EINVAL, "null argument");
+    const Geom& G = h->G;
+    const int nblk = dmrtk::tile_blocks(G, dmrtk::TY);
+    const size_t pbytes = align256((size_t)nblk * dmrtk::DIAG_SLOTS * sizeof(double));
+    const size_t fbytes = align256((size_t)G.ny * sizeof(float));
+    const size_t rbytes = 16 * sizeof(double);
+    if (pbytes + fbytes + rbytes > kScratchBytes)
+        return fail(DMRT_ESIZE,
+                    "dmrt_diag_noalloc: a %d x %d lattice needs %zu bytes of scratch, the "
+                    "fixed array holds %zu (use dmrt_diag)",
+                    G.nx, G.ny, pbytes + fbytes + rbytes, kScratchBytes);
+    HIPCHK(hipSetDevice(h->dev));
+    char* base = (char*)scratch_of(h->dev);
+    if (!base) return fail(DMRT_EDEVICE, "no scratch address for device %d", h->dev);
+    double* part = (double*)base;
+    float* front = (float*)(base + pbytes);
+    double* res = (double*)(base + pbytes + fbytes);
+    int nb = 0;
+    const int a = h->cur;
+    // every partial, row front and result is written before it is read: no
+    // clearing is needed between calls
+    HIPCHK(dmrtk::launch_diag(G, h->P, h->f[a], h->g[a], h->fl[a], h->ux, h->uy, h->eps, h->flow,
+                             part, &nb, h->stream));
+    HIPCHK(dmrtk::launch_front(G, h->fl[a], front, h->stream));
+    HIPCHK(dmrtk::launch_diag_reduce(part, nb, front, G.ny, res, h->stream));
+    double r[16];
+    HIPCHK(hipMemcpyAsync(r, res, rbytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    out->mass = r[0];
+    out->enthalpy = r[1];
+    out->liquid = r[2];
+    out->T_sum = r[3];
+    out->u_max = r[4];
+    out->active = (int64_t)llround(r[5]);
+    out->nonfinite = (int64_t)llround(r[6]);
+    out->front_mean = r[8] / G.ny;
+    out->front_max = r[9];
+    out->step = h->t;
+    return DMRT_OK;
 }
 
 int dmrt_get_derived(const dmrt_t* h, dmrt_derived* out)
@@ -1025,7 +1107,7 @@ void dmrt_destroy(dmrt_t* h)
     for (auto& g : h->graph)
         if (g) (void)hipGraphExecDestroy(g);
     if (h->base) (void)hipFree(h->base);
-    if (h->scratch) (void)hipFree(h->scratch);
+    if (h->work) (void)hipFree(h->work);
     if (h->it_sum) (void)hipFree(h->it_sum);
     if (h->r2_base) (void)hipFree(h->r2_base);
     drop_recording(h);

@@ -195,5 +195,10 @@ hipError_t launch_diag(const Geom& G, const Phys& P, const float* fcur, const fl
                        const float* eps, bool flow, double* partials, int* nblocks,
                        hipStream_t s);
 hipError_t launch_front(const Geom& G, const float* flcur, float* front, hipStream_t s);
+// res[0..7] = the block partials of launch_diag summed (slot 4: max) in block
+// order, res[8] = the sum of the ny row fronts, res[9] = their max: the
+// host-side reduction of dmrt_diag, in the same order, on the device.
+hipError_t launch_diag_reduce(const double* partials, int nblocks, const float* front, int ny,
+                              double* res, hipStream_t s);
 
 }  // namespace dmrtk

@@ -219,6 +219,31 @@ __global__ __launch_bounds__(256) void k_front(Geom G, const float* flcur, float
     }
 }
 
+// Final reduction of the diagnostics on the device, in the order of the host
+// loop of dmrt_diag (block by block, row by row), one lane per result, so
+// that both give the same bits.
+__global__ __launch_bounds__(64) void k_diag_reduce(const double* part, int nb,
+                                                    const float* front, int ny, double* res)
+{
+    const int k = (int)threadIdx.x;
+    if (k < DIAG_SLOTS) {
+        double a = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const double v = part[(long long)b * DIAG_SLOTS + k];
+            a = (k == 4) ? fmax(a, v) : a + v;
+        }
+        res[k] = a;
+    } else if (k == DIAG_SLOTS) {
+        double a = 0.0;
+        for (int r = 0; r < ny; ++r) a += front[r];
+        res[k] = a;
+    } else if (k == DIAG_SLOTS + 1) {
+        double a = 0.0;
+        for (int r = 0; r < ny; ++r) a = fmax(a, (double)front[r]);
+        res[k] = a;
+    }
+}
+
 inline dim3 tile_grid(const Geom& G) { return dim3(tile_blocks(G, TY)); }
 
 }  // namespace
@@ -271,6 +296,13 @@ hipError_t launch_diag(const Geom& G, const Phys& P, const float* fcur, const fl
     *nblocks = (int)grd.x;
     hipLaunchKernelGGL(k_diag, grd, dim3(TX, TY), 0, s, G, P, fcur, gcur, flcur, ux, uy, eps,
                        (int)flow, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_reduce(const double* partials, int nblocks, const float* front, int ny,
+                              double* res, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(64), 0, s, partials, nblocks, front, ny, res);
     return hipGetLastError();
 }
 

@@ -94,6 +94,7 @@ def _load():
         "dmrt_set_state": (C.c_int, [P, VP, VP, VP]),
         "dmrt_get_populations": (C.c_int, [P, VP, VP]),
         "dmrt_diag": (C.c_int, [P, C.POINTER(Diag)]),
+        "dmrt_diag_noalloc": (C.c_int, [P, C.POINTER(Diag)]),
         "dmrt_get_derived": (C.c_int, [P, C.POINTER(Derived)]),
         "dmrt_step_counted": (C.c_int, [P, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "dmrt_state_bytes": (C.c_int64, [P]),
@@ -278,6 +279,13 @@ class Solver:
     def diag(self):
         d = Diag()
         _check(_lib.dmrt_diag(self._h, C.byref(d)))
+        return {n: getattr(d, n) for n, _ in Diag._fields_}
+
+    def diag_noalloc(self):
+        """dmrt_diag_noalloc: the same reductions without any device
+        allocation (the library's fixed scratch array)."""
+        d = Diag()
+        _check(_lib.dmrt_diag_noalloc(self._h, C.byref(d)))
         return {n: getattr(d, n) for n, _ in Diag._fields_}
 
     def save(self):
