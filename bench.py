@@ -345,13 +345,16 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
             "liquid_cells_end": int(liq.sum())}
 
 
-def adjoint_timing(warm=200, steps=0):
+def adjoint_timing(warm=200, steps=0, record_mode=0):
     """The inverse-problem workload (512x512 cavity, Gaussian-random-field
     log K seed 1, target run seed 2, 2000 steps): wall time of the plain
-    forward run, of the recorded forward run (checkpoints every ceil(sqrt n)
-    steps) and of the adjoint (segment recomputation plus the reversed
-    steps), all from the initial state.  The first adjoint call captures the
-    reversed pass as a HIP graph; the second, timed one replays it."""
+    forward run, of the recorded forward run and of the adjoint (the
+    reversed steps, plus the segment recomputation when only checkpoints are
+    kept), all from the initial state.  record_mode 0 keeps every state of the
+    run when it fits (here 38 GB of HBM), 1 keeps checkpoints every
+    ceil(sqrt n) steps.  The first record and adjoint calls capture their HIP
+    graphs; the second, timed ones replay them (as an optimisation loop
+    does)."""
     import numpy as np
     from paper_1503_08406_amd import workloads as W
     from paper_1503_08406_amd.dmrt import Solver
@@ -361,7 +364,7 @@ def adjoint_timing(warm=200, steps=0):
     t.step(steps)
     Ft = t.fields()
     t.close()
-    s = Solver(case, graph_steps=64)
+    s = Solver(case, graph_steps=64, record_mode=record_mode)
     s.step(warm)
     s.sync()
 
@@ -374,6 +377,8 @@ def adjoint_timing(warm=200, steps=0):
 
     s.reset()
     fwd = timed(lambda: s.step(steps))
+    s.reset()
+    rec_first = timed(lambda: s.record(steps))  # captures the recording's graph
     s.reset()
     rec = timed(lambda: s.record(steps))
     F = s.fields()
@@ -388,7 +393,10 @@ def adjoint_timing(warm=200, steps=0):
     return {"workload": "inverse problem: 512x512 cavity (Sec. 4.3 setting), Ra=1e5 Da=1e-3 Ste=1 "
                         "eps=0.4, log K = log(Da H^2) + 0.5 GRF(corr 32, seed 1), target run "
                         "seed 2, L = 1/2 sum((f_l - f_l*)^2 + (T - T*)^2) after %d steps" % steps,
+            "record_mode": {0: "every state kept (fits in HBM)", 1: "sqrt(n) checkpoints, "
+                            "segments recomputed"}[record_mode],
             "steps": steps, "forward_ms": round(fwd, 3), "record_ms": round(rec, 3),
+            "record_first_call_ms": round(rec_first, 3),
             "adjoint_ms": round(adj, 3), "adjoint_first_call_ms": round(adj_first, 3),
             "adjoint_over_forward": round(adj / fwd, 3),
             "record_and_adjoint_over_forward": round((rec + adj) / fwd, 3),
@@ -618,6 +626,7 @@ def main():
                 out["batched"]["value"] / out["hbm_point"]["value"], 4)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(steps=args.adjoint_steps)
+        out["adjoint_checkpointed"] = adjoint_timing(steps=args.adjoint_steps, record_mode=1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
         out["cpu_baseline"]["small_configs"] = small_configs()

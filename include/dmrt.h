@@ -116,6 +116,12 @@ typedef struct {
     double cm_ratio;    /* (rho c_p)_m / (rho c_pl) of the matrix (sigma_mode 1), 1 */
     double ks_ratio;    /* k_s / k_l (ke_mode 1), 1                             */
     double km_ratio;    /* k_m / k_l of the matrix (ke_mode 1), 1               */
+    int32_t record_mode;/* what dmrt_record keeps for the adjoint: 0 every state of the
+                           run when n + 1 states take at most half of the free device
+                           memory, checkpoints otherwise; 1 checkpoints every
+                           ceil(sqrt(n)) steps, the adjoint recomputing each segment;
+                           2 every state (DMRT_ENOMEM if it does not fit); default 0.
+                           The gradients are the same bits in every mode          */
 } dmrt_opts;
 
 /* Lattice constants derived from the dimensionless inputs (Sec. 4.3). */
@@ -223,8 +229,12 @@ int dmrt_set_porous(dmrt_t *h, const float *eps, const float *K, const float *Fe
 
 /* Differentiation of a run (NEXT row f2: the discrete adjoint of the step).
  * dmrt_record advances n >= 1 steps like dmrt_step and keeps what the
- * adjoint needs: the state every S = ceil(sqrt(n)) steps (checkpoints), plus
- * room for one segment of S states that the adjoint recomputes.  Needs
+ * adjoint needs (record_mode of dmrt_opts): either every state of the run,
+ * each step writing its result into a slot of its own, or the state every
+ * S = ceil(sqrt(n)) steps (checkpoints) plus room for one segment of S states
+ * that the adjoint recomputes.  The launches of a recording are replayed from
+ * a HIP graph captured at the first call for n (when the handle has a
+ * stream).  Needs
  * uniform sigma and tau_T (sigma_s == sigma_l, alpha_ratio == 1).
  * dmrt_adjoint then returns, for a loss L of the fields at the end of the
  * recorded run with adjoints dL_dT and dL_dfl (nx*ny each; NULL = 0), the

@@ -113,6 +113,10 @@ struct dmrt {
     float* stage = nullptr;   // two packed nx*ny planes: terminal adjoints in, gradients out
     hipGraphExec_t adj_graph = nullptr;  // the reversed pass for rec_cap steps
     bool adj_flow = false;
+    int record_mode = 0;
+    bool rec_all = false;  // every state of the recorded run kept (no recomputation)
+    hipGraphExec_t rec_graph[2]{};  // the recording's launches from buffer parity 0 / 1
+    bool rec_graph_flow = false;
     // latent source at the pre-stream site: T*, two f_l iterates, sweep flags
     bool r2 = false;
     char* r2_base = nullptr;
@@ -181,6 +185,8 @@ int check_opts(const dmrt_opts& o)
         return fail(DMRT_EINVAL, "sigma_mode, ke_mode and latent_mode must be 0 or 1");
     if (o.store_hint < 0 || o.store_hint > 3)
         return fail(DMRT_EINVAL, "store_hint must be 0, 1, 2 or 3");
+    if (o.record_mode < 0 || o.record_mode > 2)
+        return fail(DMRT_EINVAL, "record_mode must be 0, 1 or 2");
     if (!finite_pos(o.cps_ratio) || !finite_pos(o.cm_ratio) || !finite_pos(o.ks_ratio) ||
         !finite_pos(o.km_ratio))
         return fail(DMRT_EINVAL, "cps_ratio, cm_ratio, ks_ratio, km_ratio must be > 0");
@@ -478,10 +484,21 @@ int porous_planes(dmrt* h, const float* eps, const float* K, const float* Feps,
     return DMRT_OK;
 }
 
+void drop_record_graphs(dmrt* h)
+{
+    for (auto& g : h->rec_graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
 void drop_recording(dmrt* h)
 {
     if (h->adj_graph) (void)hipGraphExecDestroy(h->adj_graph);
     h->adj_graph = nullptr;
+    drop_record_graphs(h);
+    h->rec_all = false;
     if (h->rec_base) (void)hipFree(h->rec_base);
     h->rec_base = nullptr;
     h->ckpt = h->ring = h->ls = h->la = h->ga = h->flnext = h->stage = nullptr;
@@ -491,7 +508,9 @@ void drop_recording(dmrt* h)
 // Enqueue the reversed pass over a recorded run of n steps: per segment,
 // last segment first, recompute its states into the ring (the first read
 // from its checkpoint), then one adjoint launch per step, last step first;
-// the local adjoints alternate between two buffers.
+// the local adjoints alternate between two buffers.  When the recording kept
+// every state (one segment of n steps, already in the ring) nothing is
+// recomputed.
 int enqueue_adjoint(dmrt* h)
 {
     const Geom& G = h->G;
@@ -503,13 +522,13 @@ int enqueue_adjoint(dmrt* h)
         const int64_t len = std::min(S, n - c * S);
         const float* ck = h->ckpt + (size_t)c * sb;
         auto state = [&](int64_t j) { return j == 0 ? ck : h->ring + (size_t)j * sb; };
-        if (c < C - 1) {
+        if (c < C - 1 && !h->rec_all) {
             // f_l of the state after this segment's end is the later
             // segment's state 1, about to be overwritten in the ring
             hipError_t e = dmrtk::launch_copy(h->flnext, h->ring + sb + (fq + 5) * pl, pl, h->stream);
             if (e != hipSuccess) return fail(DMRT_EDEVICE, "copy launch: %s", hipGetErrorString(e));
         }
-        for (int64_t j = 0; j < len; ++j) {
+        for (int64_t j = 0; j < len && !h->rec_all; ++j) {
             const float* a = state(j);
             float* b = h->ring + (size_t)(j + 1) * sb;
             dmrtk::StepBufs B;
@@ -551,6 +570,83 @@ int enqueue_adjoint(dmrt* h)
             if (e != hipSuccess) return fail(DMRT_EDEVICE, "adjoint launch: %s", hipGetErrorString(e));
         }
     }
+    return DMRT_OK;
+}
+
+// Buffers of one step from ring state a into ring slot b (u^k read from a).
+dmrtk::StepBufs ring_bufs(const dmrt* h, const float* a, float* b)
+{
+    const size_t pl = (size_t)h->G.plane, fq = dmrtk::FQ;
+    dmrtk::StepBufs B;
+    B.fin = a;
+    B.fout = b;
+    B.gin = a + fq * pl;
+    B.gout = b + fq * pl;
+    B.flin = a + (fq + 5) * pl;
+    B.flout = b + (fq + 5) * pl;
+    B.ux = b + (fq + 6) * pl;
+    B.uy = b + (fq + 7) * pl;
+    B.uin = a + (fq + 6) * pl;
+    B.eps = h->eps;
+    B.Ac = h->Ac;
+    B.Bc = h->Bc;
+    B.it_sum = B.it_max = nullptr;
+    B.r2f = nullptr;
+    B.r2_its = 0;
+    return B;
+}
+
+// Copy the handle's state at buffer parity p into a snapshot of ADJ_STATE
+// planes (f, g, f_l, u), or back (copy kernels, so that a graph can hold them).
+hipError_t state_copy(dmrt* h, int p, float* snap, bool to_snapshot)
+{
+    const size_t pl = (size_t)h->G.plane, fq = dmrtk::FQ;
+    float* const parts[4] = {h->f[p], h->g[p], h->fl[p], h->ux};  // uy follows ux
+    const size_t planes[4] = {fq, 5, 1, 2};
+    float* q = snap;
+    for (int k = 0; k < 4; ++k) {
+        const size_t n = planes[k] * pl;
+        hipError_t e = to_snapshot ? dmrtk::launch_copy(q, parts[k], n, h->stream)
+                                   : dmrtk::launch_copy(parts[k], q, n, h->stream);
+        if (e != hipSuccess) return e;
+        q += n;
+    }
+    return hipSuccess;
+}
+
+// The launches of a recorded run of rec_n steps from buffer parity p.  With
+// every state kept: the state into checkpoint 0, each step from one ring
+// slot into the next, the last state back into the buffers at parity p.
+// With checkpoints: per segment, the state into its checkpoint, then its
+// steps in the handle's buffers.
+int enqueue_record(dmrt* h, int p)
+{
+    const size_t sb = (size_t)dmrtk::ADJ_STATE * h->G.plane;
+    const int64_t n = h->rec_n, S = h->rec_S;
+    if (h->rec_all) {
+        HIPCHK(state_copy(h, p, h->ckpt, true));
+        for (int64_t k = 0; k < n; ++k) {
+            const float* a = k == 0 ? h->ckpt : h->ring + (size_t)k * sb;
+            HIPCHK(dmrtk::launch_step(h->G, h->P, ring_bufs(h, a, h->ring + (size_t)(k + 1) * sb),
+                                      h->flow, false, h->stream));
+        }
+        HIPCHK(state_copy(h, p, h->ring + (size_t)n * sb, false));
+        return DMRT_OK;
+    }
+    const int save = h->cur;
+    h->cur = p;
+    for (int64_t c = 0, k = 0; k < n; ++c) {
+        hipError_t e = state_copy(h, h->cur, h->ckpt + (size_t)c * sb, true);
+        for (int64_t j = 0; j < S && k < n && e == hipSuccess; ++j, ++k) {
+            e = enqueue_step(h, false);
+            h->cur = 1 - h->cur;
+        }
+        if (e != hipSuccess) {
+            h->cur = save;
+            return fail(DMRT_EDEVICE, "record launch: %s", hipGetErrorString(e));
+        }
+    }
+    h->cur = save;
     return DMRT_OK;
 }
 
@@ -619,6 +715,7 @@ void dmrt_opts_default(dmrt_opts* o)
     o->cm_ratio = 1.0;
     o->ks_ratio = 1.0;
     o->km_ratio = 1.0;
+    o->record_mode = 0;
 }
 
 int dmrt_derive(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
@@ -657,6 +754,7 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     h->Ste = Ste;
     h->check_every = o.check_every;
     h->graph_steps = o.graph_steps;
+    h->record_mode = o.record_mode;
     h->stream = (hipStream_t)o.stream;
     Geom& G = h->G;
     fill_geom(G, (int)nx, (int)ny, *bc, o);
@@ -992,16 +1090,27 @@ int dmrt_record(dmrt_t* h, int64_t n)
         return fail(DMRT_EINVAL, "the adjoint needs uniform sigma and tau_T (sigma_s == sigma_l, "
                                  "alpha_ratio == 1, no thermal-model variant)");
     HIPCHK(hipSetDevice(h->dev));
-    int64_t S = 1;
-    while (S * S < n) ++S;
-    const int64_t C = (n + S - 1) / S;
     const size_t pl = (size_t)h->G.plane, sb = (size_t)dmrtk::ADJ_STATE * pl;
-    if (h->rec_cap != n) {
+    const size_t extra = ((size_t)(dmrtk::ADJ_LS + 2 * dmrtk::ADJ_LA + dmrtk::ADJ_GA + 1) * pl +
+                          2 * (size_t)h->G.nx * h->G.ny) * sizeof(float);
+    // every state: one checkpoint (state 0) and n + 1 ring slots (states 1..n)
+    const size_t all_bytes = (size_t)(n + 2) * sb * sizeof(float) + extra;
+    bool keep_all = h->record_mode == 2;
+    if (h->record_mode == 0) {
+        size_t freeb = 0, totb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totb));
+        const size_t held = (h->rec_cap == n && h->rec_all) ? all_bytes : 0;  // ours already
+        keep_all = all_bytes <= (freeb + held) / 2;
+    }
+    int64_t S = n;
+    if (!keep_all) {
+        S = 1;
+        while (S * S < n) ++S;
+    }
+    const int64_t C = (n + S - 1) / S;
+    if (h->rec_cap != n || h->rec_all != keep_all) {
         drop_recording(h);
-        const size_t total = ((size_t)C * sb + (size_t)(S + 1) * sb +
-                              (size_t)(dmrtk::ADJ_LS + 2 * dmrtk::ADJ_LA + dmrtk::ADJ_GA + 1) * pl +
-                              2 * (size_t)h->G.nx * h->G.ny) *
-                             sizeof(float);
+        const size_t total = (size_t)C * sb * sizeof(float) + (size_t)(S + 1) * sb * sizeof(float) + extra;
         hipError_t e = hipMalloc(&h->rec_base, total);
         if (e != hipSuccess) {
             h->rec_base = nullptr;
@@ -1017,21 +1126,43 @@ int dmrt_record(dmrt_t* h, int64_t n)
         h->flnext = h->ga + (size_t)dmrtk::ADJ_GA * pl;
         h->stage = h->flnext + pl;
         h->rec_cap = n;
+        h->rec_all = keep_all;
     }
-    h->rec_n = 0;
-    const size_t fb = (size_t)dmrtk::FQ * pl * sizeof(float), pb = pl * sizeof(float);
-    for (int64_t c = 0; c < C; ++c) {
-        float* q = h->ckpt + (size_t)c * sb;
-        const int a = h->cur;
-        HIPCHK(hipMemcpyAsync(q, h->f[a], fb, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(hipMemcpyAsync(q + dmrtk::FQ * pl, h->g[a], 5 * pb, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(hipMemcpyAsync(q + (dmrtk::FQ + 5) * pl, h->fl[a], pb, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(hipMemcpyAsync(q + (dmrtk::FQ + 6) * pl, h->ux, 2 * pb, hipMemcpyDeviceToDevice, h->stream));
-        int rc = dmrt_step(h, std::min(S, n - c * S));
-        if (rc) return rc;
-    }
+    if (h->rec_graph_flow != h->flow) drop_record_graphs(h);
     h->rec_n = n;
     h->rec_S = S;
+    const int p = h->cur;
+    if (h->stream) {
+        if (!h->rec_graph[p]) {
+            HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_record(h, p);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(h->stream, &graph);
+            if (rc || e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                h->rec_n = 0;
+                return rc ? rc : fail(DMRT_EDEVICE, "capture of the recording: %s", hipGetErrorString(e));
+            }
+            e = hipGraphInstantiate(&h->rec_graph[p], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                h->rec_graph[p] = nullptr;
+                h->rec_n = 0;
+                return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            h->rec_graph_flow = h->flow;
+        }
+        HIPCHK(hipGraphLaunch(h->rec_graph[p], h->stream));
+    } else {
+        int rc = enqueue_record(h, p);
+        if (rc) {
+            h->rec_n = 0;
+            return rc;
+        }
+    }
+    if (!keep_all && (n & 1)) h->cur = 1 - h->cur;
+    h->t += n;
+    if (h->check_every > 0) return check_finite(h);
     return DMRT_OK;
 }
 
