@@ -115,19 +115,25 @@ def test_adjoint_of_one_step_is_the_transpose_of_the_tangent(bc, ergun):
     assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs)
 
 
-def test_tangent_covers_melting_restart_and_freezing():
-    """A step in which some nodes melt (restart from their neighbours'
-    density) and others freeze: tangent against central differences."""
+def _phase_change_state():
+    """A random state with some solid nodes made hot enough to melt in the
+    next step (they restart from their neighbours' density) and some liquid
+    nodes cold enough to freeze."""
     case = _case(12, 9, "box", 11)
     f, g, fl = _state(case, 12)
     from oracle import lattice
     w5 = lattice()["w5"]
-    solid = np.argwhere(fl == 0)[::3]
-    liquid = np.argwhere(fl > 0)[::5]
-    for (y, x) in solid:
+    for (y, x) in np.argwhere(fl == 0)[::3]:
         g[:, y, x] = w5 * 0.6   # well above the liquidus: melts in this step
-    for (y, x) in liquid:
+    for (y, x) in np.argwhere(fl > 0)[::5]:
         g[:, y, x] = w5 * -0.6  # well below the solidus: freezes in this step
+    return case, f, g, fl
+
+
+def test_tangent_covers_melting_restart_and_freezing():
+    """A step in which some nodes melt (restart from their neighbours'
+    density) and others freeze: tangent against central differences."""
+    case, f, g, fl = _phase_change_state()
     o = _sim(case)
     o.set_state(f, g, fl)
     o.step(1)
@@ -145,6 +151,23 @@ def test_tangent_covers_melting_restart_and_freezing():
     for a, pp, mm in zip(tl, p, m):
         fd = (pp - mm) / (2 * h)
         assert np.abs(a - fd).max() < 1e-6 * np.abs(fd).max()
+
+
+def test_adjoint_is_the_transpose_across_melting_and_freezing():
+    """The dot-product identity on the step with restarts and freezing."""
+    case, f, g, fl = _phase_change_state()
+    o = _sim(case)
+    o.set_state(f, g, fl)
+    v = _direction(case, fl, 14)
+    rng = np.random.default_rng(15)
+    w = (rng.standard_normal(f.shape), rng.standard_normal(g.shape),
+         rng.standard_normal(fl.shape))
+    Jv = o.step_tl(*v)
+    JTw = o.step_ad(*w)
+    lhs = sum(float(np.sum(a * b)) for a, b in zip(Jv, w))
+    rhs = sum(float(np.sum(a * b)) for a, b in zip(v, JTw))
+    scale = sum(float(np.sum(np.abs(a * b))) for a, b in zip(Jv, w))
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs)
 
 
 def _run_fields(case, steps, eps, K):

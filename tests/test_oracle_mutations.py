@@ -19,13 +19,21 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "dmrt_oracle.c")
 
 PINS = ["slab_flow", "pressure_level", "box_rest", "solid_channel"]
+DERIV_PINS = ["tangent_fd", "tangent_fd_phase", "dot_product", "dot_product_phase",
+              "run_gradient"]
 
 _RUNNER = r"""
 import json, sys
 sys.path[:0] = [%(root)r, %(tests)r]
 import oracle
 import test_oracle_pins as P
+import test_oracle_adjoint as D
 pins = {
+    "tangent_fd": lambda: D.test_tangent_of_one_step_matches_central_differences("mixed", True),
+    "tangent_fd_phase": lambda: D.test_tangent_covers_melting_restart_and_freezing(),
+    "dot_product": lambda: D.test_adjoint_of_one_step_is_the_transpose_of_the_tangent("mixed", True),
+    "dot_product_phase": lambda: D.test_adjoint_is_the_transpose_across_melting_and_freezing(),
+    "run_gradient": lambda: D.test_gradient_of_a_run_matches_central_differences("convection"),
     "slab_flow": lambda: P.check_slab_flow_follows_brinkman(),
     "pressure_level": lambda: P.check_flow_independent_of_pressure_level(oracle),
     "box_rest": lambda: P.test_closed_box_at_rest_keeps_any_density(oracle),
@@ -44,7 +52,8 @@ print(json.dumps(out))
 WALL_EQ = "orc_feq(s->rho[c], 0, 0, phi, feq_w);"
 NODE_EQ = "orc_feq(s->rho[c], s->ux[c], s->uy[c], phi, feq_x);"
 RESTART = "double rbar = cnt ? rsum / cnt : RHO0;"
-LIQ_SRC = "s->chi[sc = (long)sy * nx + sx]"
+LIQ_SRC = """s->chi[sc = (long)sy * nx + sx]) {
+                    s->fnew[c * Q9 + i] = s->fpost[sc * Q9 + i];"""
 NEE = """                } else {
                     s->fnew[c * Q9 + i] = feq_w[i] + s->fpost[c * Q9 + i] - feq_x[i];
                 }"""
@@ -57,7 +66,8 @@ MUTATIONS = {
     "melted node restarts at rho0":
         (RESTART, "double rbar = RHO0; (void)rsum;", ["pressure_level"]),
     "pull from solid nodes without extrapolation":
-        (LIQ_SRC, "((sc = (long)sy * nx + sx) >= 0)", ["pressure_level", "solid_channel"]),
+        (LIQ_SRC, LIQ_SRC.replace("s->chi[sc = (long)sy * nx + sx]", "((sc = (long)sy * nx + sx) >= 0)"),
+         ["pressure_level", "solid_channel"]),
     "half-way bounce-back at solid sources":
         (NEE, """                } else if (source_node(s, x, y, s->L9.ex[i], s->L9.ey[i], &sx, &sy, &side)) {
                     %s
@@ -73,7 +83,30 @@ MUTATIONS = {
 }
 
 
-def _build_and_run(tmp_path, tag, text=None, repl=None):
+# Mistakes in the oracle's discrete derivatives (tangent-linear model and
+# its transpose): name: (text, replacement, pins that must fail).
+DERIV_MUTATIONS = {
+    "wrong sign of the (1 - eps)^2 factor in dK_e":
+        ("- 2.0 * deps / (1.0 - w->eps) +", "+ 2.0 * deps / (1.0 - w->eps) +",
+         ["tangent_fd", "dot_product"]),
+    "moment adjoint relaxed with s instead of 1 - s":
+        ("        bm[a] = (1.0 - sv[a]) * bmp[a];", "        bm[a] = sv[a] * bmp[a];",
+         ["dot_product", "run_gradient"]),
+    "adjoint of the g pull kept at the receiving node":
+        ("                    bgp[((long)sy * nx + sx) * Q5 + i] += b;",
+         "                    bgp[c * Q5 + i] += b;", ["dot_product", "run_gradient"]),
+    "latent source tangent without the porosity of a":
+        ("(dTs + a * dfl[c] + (fk - fn) * da) / (dTm + a)", "(dTs + a * dfl[c]) / (dTm + a)",
+         ["tangent_fd", "dot_product"]),
+    "restart adjoint not divided by the neighbour count":
+        ("brho[nb[k]] += br / cnt;", "brho[nb[k]] += br;", ["dot_product_phase", "run_gradient"]),
+    "enthalpy derivative also on the clamped branches":
+        ("(fn > 0 && fn < 1) ? (dTs", "(fn >= 0 && fn <= 1) ? (dTs",
+         ["tangent_fd", "tangent_fd_phase", "dot_product"]),
+}
+
+
+def _build_and_run(tmp_path, tag, text=None, repl=None, pins=None):
     src = open(SRC).read()
     if text is not None:
         assert src.count(text) == 1, "mutation target not unique: %r" % text
@@ -86,7 +119,7 @@ def _build_and_run(tmp_path, tag, text=None, repl=None):
     subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-I", hdr, "-o", lib, str(d / "o.c"),
                            "-lm"])
     env = dict(os.environ, DMRT_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
-    code = _RUNNER % dict(root=ROOT, tests=os.path.join(ROOT, "tests"), pins=PINS)
+    code = _RUNNER % dict(root=ROOT, tests=os.path.join(ROOT, "tests"), pins=pins or PINS)
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
@@ -94,7 +127,7 @@ def _build_and_run(tmp_path, tag, text=None, repl=None):
 
 
 def test_unchanged_copy_passes_every_pin(tmp_path):
-    res = _build_and_run(tmp_path, "control")
+    res = _build_and_run(tmp_path, "control", pins=PINS + DERIV_PINS)
     assert all(v == "pass" for v in res.values()), res
 
 
@@ -102,6 +135,15 @@ def test_unchanged_copy_passes_every_pin(tmp_path):
 def test_planted_mistake_fails_its_pins(tmp_path, name):
     text, repl, must_fail = MUTATIONS[name]
     res = _build_and_run(tmp_path, "m", text, repl)
+    print(name, res)
+    for pin in must_fail:
+        assert res[pin] != "pass", (name, pin, res)
+
+
+@pytest.mark.parametrize("name", list(DERIV_MUTATIONS))
+def test_planted_derivative_mistake_fails_its_pins(tmp_path, name):
+    text, repl, must_fail = DERIV_MUTATIONS[name]
+    res = _build_and_run(tmp_path, "d", text, repl, pins=DERIV_PINS)
     print(name, res)
     for pin in must_fail:
         assert res[pin] != "pass", (name, pin, res)
