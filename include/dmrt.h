@@ -122,6 +122,12 @@ typedef struct {
                            ceil(sqrt(n)) steps, the adjoint recomputing each segment;
                            2 every state (DMRT_ENOMEM if it does not fit); default 0.
                            The gradients are the same bits in every mode          */
+    int32_t steps_per_launch; /* 0 or 1: one time step per launch; 2: two steps per
+                           launch where the launch allows it (default thermal model,
+                           R1, arrays within 4 GB, block_rows 4, one node per lane):
+                           the intermediate state stays in LDS, so a node update
+                           moves half the bytes.  The results are the same bits;
+                           default 1                                              */
 } dmrt_opts;
 
 /* Lattice constants derived from the dimensionless inputs (Sec. 4.3). */

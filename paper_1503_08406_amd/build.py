@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmrt.so")
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("dmrt_step.hip", "dmrt_batch.hip", "dmrt_adjoint.hip", "dmrt_kernels.hip", "dmrt_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("dmrt_step.hip", "dmrt_step2.hip", "dmrt_batch.hip", "dmrt_adjoint.hip", "dmrt_kernels.hip", "dmrt_api.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

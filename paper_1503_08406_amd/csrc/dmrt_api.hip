@@ -97,11 +97,14 @@ struct dmrt {
     int check_every = 0, graph_steps = 0;
     char* base = nullptr;
     float *f[2]{}, *g[2]{}, *fl[2]{};
-    float *ux = nullptr, *uy = nullptr, *eps = nullptr, *Ac = nullptr, *Bc = nullptr;
+    float* u[2]{};  // u_x plane then u_y plane of the state in buffer parity 0 / 1
+    float *eps = nullptr, *Ac = nullptr, *Bc = nullptr;
     char* work = nullptr;  // device work space of the field, population and diagnostics copies
     size_t work_bytes = 0;
     int *it_sum = nullptr, *it_max = nullptr;
     hipGraphExec_t graph[2]{};
+    int graph_flip[2]{};  // buffer parity changes of a replay of graph[p]
+    bool two_step = false;  // steps run two per launch (k_step2) where possible
     double ergun_c = 175.0;
     bool feps_given = false;
     // recorded run for the adjoint: checkpoints every rec_S steps, the ring
@@ -187,6 +190,8 @@ int check_opts(const dmrt_opts& o)
         return fail(DMRT_EINVAL, "store_hint must be 0, 1, 2 or 3");
     if (o.record_mode < 0 || o.record_mode > 2)
         return fail(DMRT_EINVAL, "record_mode must be 0, 1 or 2");
+    if (o.steps_per_launch < 0 || o.steps_per_launch > 2)
+        return fail(DMRT_EINVAL, "steps_per_launch must be 0, 1 or 2");
     if (!finite_pos(o.cps_ratio) || !finite_pos(o.cm_ratio) || !finite_pos(o.ks_ratio) ||
         !finite_pos(o.km_ratio))
         return fail(DMRT_EINVAL, "cps_ratio, cm_ratio, ks_ratio, km_ratio must be > 0");
@@ -277,7 +282,7 @@ void fill_geom(Geom& G, int nx, int ny, const dmrt_bc& bc, const dmrt_opts& o)
         G.T_wall[k] = (float)bc.T_wall[k];
     }
     G.block_rows = o.block_rows ? o.block_rows : 4;
-    G.store = store_policy(o.store_hint, (size_t)G.plane * 4 * (2 * dmrtk::FQ + 2 * 5 + 2 + 2 + 3));
+    G.store = store_policy(o.store_hint, (size_t)G.plane * 4 * (2 * dmrtk::FQ + 2 * 5 + 2 + 4 + 3));
     // the thermal-model variants run one node per lane
     const bool variant = o.sigma_mode || o.ke_mode || o.latent_mode;
     G.cells_per_lane = (o.cells_per_lane && !variant) ? o.cells_per_lane : 1;
@@ -324,9 +329,9 @@ dmrtk::StepBufs bufs(dmrt* h, bool counted)
     B.gout = h->g[b];
     B.flin = h->fl[a];
     B.flout = h->fl[b];
-    B.ux = h->ux;
-    B.uy = h->uy;
-    B.uin = nullptr;
+    B.ux = h->u[b];
+    B.uy = h->u[b] + h->G.plane;
+    B.uin = h->u[a];
     B.eps = h->eps;
     B.Ac = h->Ac;
     B.Bc = h->Bc;
@@ -355,6 +360,14 @@ hipError_t enqueue_step(dmrt* h, bool counted)
     return dmrtk::launch_step(h->G, h->P, bufs(h, counted), h->flow, counted, h->stream);
 }
 
+// Two steps in one launch (k_step2) from buffer parity h->cur into the other.
+bool use_two_step(const dmrt* h) { return h->two_step && !h->r2; }
+
+hipError_t enqueue_step2(dmrt* h)
+{
+    return dmrtk::launch_step2(h->G, h->P, bufs(h, false), h->flow, h->stream);
+}
+
 // One plain step; flips the buffer index.
 int step_once(dmrt* h, bool counted)
 {
@@ -371,8 +384,10 @@ int build_graph(dmrt* h, int p)
     const int64_t tsave = h->t;
     h->cur = p;
     HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < h->graph_steps; ++k) {
-        hipError_t e = enqueue_step(h, false);
+    const bool two = use_two_step(h);
+    const int launches = two ? h->graph_steps / 2 : h->graph_steps;
+    for (int k = 0; k < launches; ++k) {
+        hipError_t e = two ? enqueue_step2(h) : enqueue_step(h, false);
         h->cur = 1 - h->cur;
         if (e != hipSuccess) {
             hipGraph_t gdrop = nullptr;
@@ -393,6 +408,7 @@ int build_graph(dmrt* h, int p)
         h->graph[p] = nullptr;
         return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
+    h->graph_flip[p] = launches & 1;
     return DMRT_OK;
 }
 
@@ -408,7 +424,7 @@ int diag_impl(dmrt* h, dmrt_diag_t* out)
     float* front = (float*)(h->work + pbytes);
     int nb = 0;
     const int a = h->cur;
-    HIPCHK(dmrtk::launch_diag(G, h->P, h->f[a], h->g[a], h->fl[a], h->ux, h->uy, h->eps, h->flow,
+    HIPCHK(dmrtk::launch_diag(G, h->P, h->f[a], h->g[a], h->fl[a], h->u[a], h->u[a] + G.plane, h->eps, h->flow,
                              part, &nb, h->stream));
     HIPCHK(dmrtk::launch_front(G, h->fl[a], front, h->stream));
     std::vector<double> hp((size_t)nb * dmrtk::DIAG_SLOTS);
@@ -601,7 +617,7 @@ dmrtk::StepBufs ring_bufs(const dmrt* h, const float* a, float* b)
 hipError_t state_copy(dmrt* h, int p, float* snap, bool to_snapshot)
 {
     const size_t pl = (size_t)h->G.plane, fq = dmrtk::FQ;
-    float* const parts[4] = {h->f[p], h->g[p], h->fl[p], h->ux};  // uy follows ux
+    float* const parts[4] = {h->f[p], h->g[p], h->fl[p], h->u[p]};  // u_y follows u_x
     const size_t planes[4] = {fq, 5, 1, 2};
     float* q = snap;
     for (int k = 0; k < 4; ++k) {
@@ -716,6 +732,7 @@ void dmrt_opts_default(dmrt_opts* o)
     o->ks_ratio = 1.0;
     o->km_ratio = 1.0;
     o->record_mode = 0;
+    o->steps_per_launch = 1;
 }
 
 int dmrt_derive(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
@@ -760,6 +777,7 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     fill_geom(G, (int)nx, (int)ny, *bc, o);
     fill_phys(h->P, h->D, h->Ste, o);
     h->flow = d.gbeta != 0.0;
+    h->two_step = o.steps_per_launch == 2 && !o.latent_mode && dmrtk::step2_supported(G, h->P);
 
     auto bail = [&](int code) {
         dmrt_destroy(h);
@@ -778,7 +796,7 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
 
     // Device memory: one allocation, 256-byte aligned sub-arrays.
     const size_t plane_b = align256(pcell * sizeof(float));
-    const size_t total = plane_b * (2 * dmrtk::FQ + 2 * 5 + 2 + 2 + 3);
+    const size_t total = plane_b * (2 * dmrtk::FQ + 2 * 5 + 2 + 4 + 3);
     e = hipMalloc(&h->base, total);
     if (e != hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE,
@@ -795,8 +813,8 @@ int dmrt_create(const dmrt_grid* grid, const float* eps, const float* K, const f
     h->g[1] = take(5);
     h->fl[0] = take(1);
     h->fl[1] = take(1);
-    h->ux = take(1);
-    h->uy = take(1);
+    h->u[0] = take(2);
+    h->u[1] = take(2);
     h->eps = take(1);
     h->Ac = take(1);
     h->Bc = take(1);
@@ -848,8 +866,8 @@ int dmrt_set_state(dmrt_t* h, const float* f, const float* g, const float* fl)
     }
     if (f) set_flow(h, true);  // a given velocity field may move without gravity
     const int a = h->cur;
-    HIPCHK(dmrtk::launch_load_state(G, h->P, df, dg, dfl, h->f[a], h->g[a], h->fl[a], h->ux, h->uy,
-                                   h->eps, h->Ac, h->Bc, h->flow, h->stream));
+    HIPCHK(dmrtk::launch_load_state(G, h->P, df, dg, dfl, h->f[a], h->g[a], h->fl[a], h->u[a],
+                                   h->u[a] + G.plane, h->eps, h->Ac, h->Bc, h->flow, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return DMRT_OK;
 }
@@ -870,8 +888,14 @@ int dmrt_step(dmrt_t* h, int64_t n)
                 if (rc) return rc;
             }
             HIPCHK(hipGraphLaunch(h->graph[p], h->stream));
-            h->t += h->graph_steps;  // even count: buffer parity unchanged
+            h->cur = p ^ h->graph_flip[p];
+            h->t += h->graph_steps;
             chunk = h->graph_steps;
+        } else if (n >= 2 && use_two_step(h)) {
+            HIPCHK(enqueue_step2(h));
+            h->cur = 1 - h->cur;
+            h->t += 2;
+            chunk = 2;
         } else {
             int rc = step_once(h, false);
             if (rc) return rc;
@@ -929,7 +953,8 @@ int dmrt_fields(dmrt_t* h, float* T, float* ux, float* uy, float* fl)
     if (rc) return rc;
     float* s = (float*)h->work;
     const int a = h->cur;
-    HIPCHK(dmrtk::launch_fields(G, h->g[a], h->fl[a], h->ux, h->uy, h->flow, s, h->stream));
+    HIPCHK(dmrtk::launch_fields(G, h->g[a], h->fl[a], h->u[a], h->u[a] + G.plane, h->flow, s,
+                                h->stream));
     float* dst[4] = {T, ux, uy, fl};
     for (int k = 0; k < 4; ++k)
         if (dst[k]) HIPCHK(hipMemcpyAsync(dst[k], s + k * ncell, ncell * 4, hipMemcpyDefault, h->stream));
@@ -985,7 +1010,7 @@ int dmrt_diag_noalloc(dmrt_t* h, dmrt_diag_t* out)
     const int a = h->cur;
     // every partial, row front and result is written before it is read: no
     // clearing is needed between calls
-    HIPCHK(dmrtk::launch_diag(G, h->P, h->f[a], h->g[a], h->fl[a], h->ux, h->uy, h->eps, h->flow,
+    HIPCHK(dmrtk::launch_diag(G, h->P, h->f[a], h->g[a], h->fl[a], h->u[a], h->u[a] + G.plane, h->eps, h->flow,
                              part, &nb, h->stream));
     HIPCHK(dmrtk::launch_front(G, h->fl[a], front, h->stream));
     HIPCHK(dmrtk::launch_diag_reduce(part, nb, front, G.ny, res, h->stream));
@@ -1034,8 +1059,7 @@ int dmrt_save(dmrt_t* h, void* buf, size_t cap)
     HIPCHK(hipMemcpyAsync(p, h->f[a], fq * pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipMemcpyAsync(p + fq * pb, h->g[a], 5 * pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipMemcpyAsync(p + (fq + 5) * pb, h->fl[a], pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(p + (fq + 6) * pb, h->ux, pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(p + (fq + 7) * pb, h->uy, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(p + (fq + 6) * pb, h->u[a], 2 * pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return DMRT_OK;
 }
@@ -1057,8 +1081,7 @@ int dmrt_load(dmrt_t* h, const void* buf, size_t n)
     HIPCHK(hipMemcpyAsync(h->f[a], p, fq * pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipMemcpyAsync(h->g[a], p + fq * pb, 5 * pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipMemcpyAsync(h->fl[a], p + (fq + 5) * pb, pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(h->ux, p + (fq + 6) * pb, pb, hipMemcpyDefault, h->stream));
-    HIPCHK(hipMemcpyAsync(h->uy, p + (fq + 7) * pb, pb, hipMemcpyDefault, h->stream));
+    HIPCHK(hipMemcpyAsync(h->u[a], p + (fq + 6) * pb, 2 * pb, hipMemcpyDefault, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->t = (int64_t)hdr[4];
     if (hdr[5] != 0) set_flow(h, true);

@@ -72,7 +72,7 @@ struct StepBufs {
     float* __restrict__ flout;
     float* __restrict__ ux;        // u^{k+1} (ux plane, then the uy plane)
     float* __restrict__ uy;
-    const float* __restrict__ uin; // u^k when it lives elsewhere; null: read ux/uy
+    const float* __restrict__ uin; // u^k when it lives elsewhere; null: read ux/uy (in place)
     const float* __restrict__ eps;
     const float* __restrict__ Ac;  // phi nu_l / (K (1-phi)^2): Darcy coefficient
     const float* __restrict__ Bc;  // phi F_eps / (sqrt(K) (1-phi)): Forchheimer
@@ -84,6 +84,13 @@ struct StepBufs {
 
 hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flow,
                        bool counted, hipStream_t s);
+
+// Two time steps in one launch (dmrt_step2.hip): reads the state in B's
+// input buffers, writes the state two steps later into its output buffers
+// (u double-buffered: B.uin holds u^k).  For the default thermal model,
+// 32-bit offsets, the 4-row launch shape and one node per lane.
+bool step2_supported(const Geom& G, const Phys& P);
+hipError_t launch_step2(const Geom& G, const Phys& P, const StepBufs& B, bool flow, hipStream_t s);
 
 // One step with the latent source at the pre-stream site (R2): T* of every
 // node (ts), at most P.fl_maxit Jacobi sweeps of f_l over the lattice

@@ -236,38 +236,117 @@ __device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, cons
     }
 }
 
-// Flow part of a node with f_l^{k+1} > 0 (Sec. 4): pull f_i(x) = f+_i(x -
-// e_i) from liquid sources; a wall or solid source gives f_i^eq(rho, 0) +
-// f+_i(x) - f_i^eq(rho, u^k; varphi^k) (rho cancels); a node that melted in
-// this step restarts at rest at the mean start-of-step density of its
-// liquid neighbours (rho0 if none).  Then the velocity closure and the MRT
-// collision with forcing; stores f+, rho - 1 and u^{k+1}.
+// Pull sources of the flow populations at a node: bit i set when the source
+// of direction i lies behind a wall (x-, y-, x+, y+ and the four diagonals).
+struct FlowWalls {
+    bool w[9];
+    __device__ __forceinline__ FlowWalls(const Geom& G, int x, int y)
+    {
+        const bool wxm = (x == 0) & !G.per_x, wxp = (x == G.nx - 1) & !G.per_x;
+        const bool wym = (y == 0) & !G.per_y, wyp = (y == G.ny - 1) & !G.per_y;
+        w[0] = false;
+        w[1] = wxm;
+        w[2] = wym;
+        w[3] = wxp;
+        w[4] = wyp;
+        w[5] = wxm | wym;
+        w[6] = wxp | wym;
+        w[7] = wxp | wyp;
+        w[8] = wxm | wyp;
+    }
+};
+
+// Pre-collision deviations of a node that was liquid at the start of the
+// step (Sec. 4): pulled populations d_i = f+_i(x - e_i) where the source is
+// a liquid node; a wall or solid source gives f_i^eq(rho, 0) + f+_i(x) -
+// f_i^eq(rho, u^k; varphi^k), rho cancelling.  v: neighbour f_l (0-7, the
+// sources of directions 1-8), pulls (8-16), own f+_1..8 (17-24), u^k (25-26).
+__device__ __forceinline__ void flow_gather_liquid(const float (&v)[27], const FlowWalls& W,
+                                                   float eps, float flk, float (&d)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = v[8 + i];
+    float own[9];  // this node's own f+_i(x), for extrapolated directions
+    own[0] = 0.0f;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) own[i] = v[16 + i];
+    const float uxk = v[25], uyk = v[26];
+    // bit i set: the source of direction i is a liquid node
+    unsigned liq = 0u;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) liq |= (unsigned)(!W.w[i] & (v[i - 1] > 0.0f)) << i;
+    // a wall or solid source: computed for every direction and selected, so
+    // the loads are used on every path and stay in one batch
+    const float iph = frcp(eps * flk);
+    const float uu = 1.5f * (uxk * uxk + uyk * uyk) * iph;
+    const float eu[9] = {0.0f, uxk, uyk, -uxk, -uyk, uxk + uyk, uyk - uxk, -uxk - uyk, uxk - uyk};
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const float e = eu[i];
+        const float nee = own[i] - w9(i) * (3.0f * e + 4.5f * e * e * iph - uu);
+        d[i] = (liq & (1u << i)) ? d[i] : nee;
+    }
+}
+
+// A node that melted in this step restarts at rest at the mean start-of-step
+// density of its liquid lattice neighbours (rho0 if none): nf, nr are the
+// neighbours' f_l and rho - 1 (sources of directions 1-8).
+__device__ __forceinline__ void flow_gather_restart(const float (&nf)[8], const float (&nr)[8],
+                                                    const FlowWalls& W, float (&d)[9])
+{
+    float rsum = 0.0f;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!W.w[k + 1] && nf[k] > 0.0f) {
+            rsum += nr[k];
+            ++cnt;
+        }
+    }
+    const float drho = cnt ? rsum * frcp((float)cnt) : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = w9(i) * drho;
+}
+
+// rho - 1 of post-collision deviations, summed in population order.
+__device__ __forceinline__ float rho_dev(const float (&d)[9])
+{
+    float r = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r += d[i];
+    return r;
+}
+
+// Flow part of a node with f_l^{k+1} > 0 (Sec. 4), up to its post-collision
+// populations: pull f_i(x) = f+_i(x - e_i) from liquid sources; a wall or
+// solid source gives the extrapolation of flow_gather_liquid; a node that
+// melted in this step restarts at rest (flow_gather_restart).  Then the
+// velocity closure and the MRT collision with forcing.  Every load of the
+// node is issued in one batch; values are selected afterwards, so no load
+// waits behind a data-dependent branch.
 template <class IO, bool USTAT>
-__device__ __forceinline__ void node_flow(const Geom& G, const Phys& P, const Arrays<IO>& A,
-                                          int x, int y, float flk, float fl1, float T1,
-                                          float eps, float& ux, float& uy)
+__device__ __forceinline__ void node_flow_core(const Geom& G, const Phys& P, const Arrays<IO>& A,
+                                               int x, int y, float flk, float fl1, float T1,
+                                               float eps, float (&d)[9], float& ux, float& uy,
+                                               typename IO::off_t& o_out)
 {
     using off_t = typename IO::off_t;
     const off_t pb = A.pb;
-    const IO &fin = A.fin, &fout = A.fout, &flin = A.flin, &uv = A.uv;
+    const IO &fin = A.fin, &flin = A.flin;
     Node<IO> n;
     node_geometry(G, x, y, n);
     const off_t o = n.o, o1 = n.o1, o2 = n.o2, o3 = n.o3, o4 = n.o4;
-    const bool wxm = (x == 0) & !G.per_x, wxp = (x == G.nx - 1) & !G.per_x;
-    const bool wym = (y == 0) & !G.per_y, wyp = (y == G.ny - 1) & !G.per_y;
-    const bool w5 = wxm | wym, w6 = wxp | wym, w7 = wxp | wyp, w8 = wxm | wyp;
+    const FlowWalls W(G, x, y);
     const off_t pitch = (off_t)G.pitch;
     const off_t rm = (off_t)n.ym * pitch, rp = (off_t)n.yp * pitch;
-    const off_t o5 = w5 ? o : (rm + (off_t)n.xm) * 4u;
-    const off_t o6 = w6 ? o : (rm + (off_t)n.xp) * 4u;
-    const off_t o7 = w7 ? o : (rp + (off_t)n.xp) * 4u;
-    const off_t o8 = w8 ? o : (rp + (off_t)n.xm) * 4u;
+    const off_t o5 = W.w[5] ? o : (rm + (off_t)n.xm) * 4u;
+    const off_t o6 = W.w[6] ? o : (rm + (off_t)n.xp) * 4u;
+    const off_t o7 = W.w[7] ? o : (rp + (off_t)n.xp) * 4u;
+    const off_t o8 = W.w[8] ? o : (rp + (off_t)n.xm) * 4u;
     const float Ac = USTAT ? A.Ac_u : A.stat.ld(o, pb);
     const float Bc = USTAT ? A.Bc_u : A.stat.ld(o, 2 * pb);
+    o_out = o;
 
-    // every load of the node is issued in one batch; values are selected
-    // afterwards, so no load waits behind a data-dependent branch
-    float d[9];
     if (flk > 0.0f) {
         float v[27];  // neighbour f_l (0-7), pulls (8-16), own f+_1..8 (17-24), u^k
         v[0] = flin.ld(o1, 0);
@@ -292,38 +371,10 @@ __device__ __forceinline__ void node_flow(const Geom& G, const Phys& P, const Ar
         v[25] = A.uvin.ld(o, 0);
         v[26] = A.uvin.ld(o, pb);
         pin_loads(v);
-        const float n1 = v[0], n2 = v[1], n3 = v[2], n4 = v[3];
-        const float n5 = v[4], n6 = v[5], n7 = v[6], n8 = v[7];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = v[8 + i];
-        float own[9];  // this node's own f+_i(x), for extrapolated directions
-        own[0] = 0.0f;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) own[i] = v[16 + i];
-        const float uxk = v[25], uyk = v[26];
-        // bit i set: the source of direction i is a liquid node
-        const unsigned liq =
-            (unsigned)(!wxm & (n1 > 0.0f)) << 1 | (unsigned)(!wym & (n2 > 0.0f)) << 2 |
-            (unsigned)(!wxp & (n3 > 0.0f)) << 3 | (unsigned)(!wyp & (n4 > 0.0f)) << 4 |
-            (unsigned)(!w5 & (n5 > 0.0f)) << 5 | (unsigned)(!w6 & (n6 > 0.0f)) << 6 |
-            (unsigned)(!w7 & (n7 > 0.0f)) << 7 | (unsigned)(!w8 & (n8 > 0.0f)) << 8;
-        // a wall or solid source gives f_i^eq(rho, 0) + f+_i(x) - f_i^eq(rho,
-        // u^k; varphi^k); computed for every direction and selected, so the
-        // loads above are used on every path and stay in one batch
-        const float iph = frcp(eps * flk);
-        const float uu = 1.5f * (uxk * uxk + uyk * uyk) * iph;
-        const float eu[9] = {0.0f, uxk, uyk, -uxk, -uyk, uxk + uyk, uyk - uxk, -uxk - uyk, uxk - uyk};
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const float e = eu[i];
-            const float nee = own[i] - w9(i) * (3.0f * e + 4.5f * e * e * iph - uu);
-            d[i] = (liq & (1u << i)) ? d[i] : nee;
-        }
+        flow_gather_liquid(v, W, eps, flk, d);
     } else {
-        // restart at rest at the mean start-of-step density of the liquid
-        // neighbours: their f_l and stored rho - 1 in one batch
+        // their f_l and stored rho - 1 in one batch
         const off_t on[8] = {o1, o2, o3, o4, o5, o6, o7, o8};
-        const bool wn[8] = {wxm, wym, wxp, wyp, w5, w6, w7, w8};
         float nf[8], nr[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -332,29 +383,27 @@ __device__ __forceinline__ void node_flow(const Geom& G, const Phys& P, const Ar
         }
         pin_loads(nf);
         pin_loads(nr);
-        float rsum = 0.0f;
-        int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (!wn[k] && nf[k] > 0.0f) {
-                rsum += nr[k];
-                ++cnt;
-            }
-        }
-        const float drho = cnt ? rsum * frcp((float)cnt) : 0.0f;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = w9(i) * drho;
+        flow_gather_restart(nf, nr, W, d);
     }
     flow_collide(d, fl1, eps, Ac, Bc, T1, P, ux, uy);
-    float r = 0.0f;  // rho - 1, summed in population order
+}
+
+// The flow part of a node with its stores: f+, rho - 1 and u^{k+1}.
+template <class IO, bool USTAT>
+__device__ __forceinline__ void node_flow(const Geom& G, const Phys& P, const Arrays<IO>& A,
+                                          int x, int y, float flk, float fl1, float T1,
+                                          float eps, float& ux, float& uy)
+{
+    using off_t = typename IO::off_t;
+    const off_t pb = A.pb;
+    float d[9];
+    off_t o;
+    node_flow_core<IO, USTAT>(G, P, A, x, y, flk, fl1, T1, eps, d, ux, uy, o);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        fout.st(o, (off_t)i * pb, d[i]);
-        r += d[i];
-    }
-    fout.st(o, 9 * pb, r);
-    uv.st(o, 0, ux);
-    uv.st(o, pb, uy);
+    for (int i = 0; i < 9; ++i) A.fout.st(o, (off_t)i * pb, d[i]);
+    A.fout.st(o, 9 * pb, rho_dev(d));
+    A.uv.st(o, 0, ux);
+    A.uv.st(o, pb, uy);
 }
 
 // D2Q5 MRT collision (Eqs. 35, 37) and the stores of g+ and f_l^{k+1}.

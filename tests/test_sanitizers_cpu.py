@@ -40,8 +40,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not found")
 def test_library_host_code_under_sanitizers(tmp_path):
     csrc = os.path.join(ROOT, "paper_1503_08406_amd", "csrc")
-    srcs = [os.path.join(csrc, n) for n in ("dmrt_step.hip", "dmrt_batch.hip", "dmrt_adjoint.hip",
-                                            "dmrt_kernels.hip", "dmrt_api.hip")]
+    srcs = sorted(os.path.join(csrc, n) for n in os.listdir(csrc) if n.endswith(".hip"))
     exe = str(tmp_path / "abi_san")
     # sanitizers for the host pass only: each flag behind -Xarch_host
     host_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
