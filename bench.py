@@ -20,16 +20,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
-# Algorithmic bytes per cell update (float32): a cell where the flow is solved
-# reads and writes its 9 + 5 populations and f_l and reads the three porous
-# fields; a solid cell moves only the 5 thermal populations, f_l and porosity.
+# Algorithmic bytes per cell and launch (float32): a cell where the flow is
+# solved reads and writes its 9 + 5 populations and f_l and reads the three
+# porous fields; a solid cell moves only the 5 thermal populations, f_l and
+# porosity.  A launch of one step moves them once per step; a launch of two
+# steps reads the state k once and writes the state k+2 once (the state k+1
+# stays on chip), so it moves them once per two steps.
 BYTES_FLUID = 2 * (9 + 5) * 4 + 2 * 4 + 3 * 4   # 132
 BYTES_SOLID = 2 * 5 * 4 + 2 * 4 + 4             # 52
 # batched cavities have uniform porous fields: no per-node porous reads
 BYTES_FLUID_BATCH = 2 * (9 + 5) * 4 + 2 * 4      # 120
 BYTES_SOLID_BATCH = 2 * 5 * 4 + 2 * 4            # 48
 KERNEL_SRC = [os.path.join(ROOT, "paper_1503_08406_amd", "csrc", n)
-              for n in ("dmrt_step.hip", "dmrt_node.h", "dmrt_device.h", "dmrt_internal.h")]
+              for n in ("dmrt_step.hip", "dmrt_step2.hip", "dmrt_tile2.h", "dmrt_node.h",
+                        "dmrt_device.h", "dmrt_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic_cavity1024.json")
 TRAFFIC_FILE_4096 = os.path.join(ROOT, "profiles", "step_traffic_cavity4096.json")
 
@@ -146,7 +150,7 @@ def window_accounting(case, buf, steps, samples, **over):
 def repeats(case, buf, steps, n=5, **over):
     """The timed window (`steps` steps from the checkpoint `buf`) timed n
     more times, each on a fresh solver loaded from the checkpoint (HIP events
-    on its stream): per-step kernel times and their median.  Each solver
+    on its stream): kernel times per step and their median.  Each solver
     first runs one untimed graph's worth of steps from the checkpoint and is
     loaded again, so that graph capture stays out of the timed region."""
     import torch
@@ -169,6 +173,13 @@ def repeats(case, buf, steps, n=5, **over):
         s.close()
     return {"n": n, "steps": steps, "kernel_ms": [round(v, 6) for v in ms],
             "median_kernel_ms": round(sorted(ms)[n // 2], 6)}
+
+
+def step_kernel(spl):
+    """Name of the step kernel that a solver advancing spl steps per launch
+    runs (the default launch shape)."""
+    return ("k_step2 (two steps per launch, tiles of 62 x 6 nodes)" if spl == 2
+            else "k_step (flow, 4 rows, 1 node per lane)")
 
 
 def plain_copy(nbytes, copies=64, reps=10):
@@ -203,15 +214,16 @@ def plain_copy(nbytes, copies=64, reps=10):
     return {"bytes": 8 * n, "us": round(us, 3), "GBps": round(8 * n / (us * 1e-6) / 1e9, 1)}
 
 
-def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
+def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64, steps_per_launch=2):
     """The cavity workload at n x n (4096^2: 2.5 GB of state, past the
     Infinity Cache, so the step streams from HBM), timed like the main run;
-    roofline with the same phase-mixed byte model."""
+    roofline with the same phase-mixed byte model, per launch."""
     import torch
     from paper_1503_08406_amd import workloads as W
     from paper_1503_08406_amd.dmrt import Solver
     case = W.cavity(nx=n, ny=n, steps=steps)
-    s = Solver(case, graph_steps=graph_steps)
+    s = Solver(case, graph_steps=graph_steps, steps_per_launch=steps_per_launch)
+    spl = s.launch_steps
     s.step(warmup)
     s.sync()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -228,8 +240,9 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
     cells = n * n
     ff = act_steps / (cells * (warmup + steps))
     bpl = (BYTES_FLUID * ff + BYTES_SOLID * (1 - ff)) * cells
+    launch_ms = kern_ms * spl
     cp = plain_copy(bpl)
-    cp["frac_of_copy"] = round(cp["us"] / (kern_ms * 1e3), 3)
+    cp["frac_of_copy"] = round(cp["us"] / (launch_ms * 1e3), 3)
     # measured HBM traffic of this kernel at this size (rocprofv3 FETCH_SIZE /
     # WRITE_SIZE over steps 10..210), valid while the kernel source is the one
     # that was measured; its liquid fraction is stated beside it
@@ -238,29 +251,34 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64):
         tr = json.load(open(TRAFFIC_FILE_4096))
         if tr.get("kernel_sha") == kernel_hash():
             traffic = {"bytes": tr["bytes_per_launch"], "fluid_fraction": tr["fluid_fraction"],
-                       "GBps": round(tr["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9, 1)}
+                       "GBps": round(tr["bytes_per_launch"] / (launch_ms * 1e-3) / 1e9, 1)}
     return {"workload": "the same cavity at %dx%d (%.2f GB of state), steps %d..%d"
                         % (n, n, cells * 148 / 1e9, warmup, warmup + steps),
             "value": round(cells * steps / wall / 1e6, 2), "unit": "MLUPS",
-            "kernel_ms": round(kern_ms, 6),
-            "roofline": {"bound": "hbm", "achieved": round(bpl / (kern_ms * 1e-3) / 1e9, 1),
+            "kernel_ms_per_step": round(kern_ms, 6), "steps_per_launch": spl,
+            "roofline": {"bound": "hbm", "achieved": round(bpl / (launch_ms * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                         "frac": round(bpl / (kern_ms * 1e-3) / HBM_PEAK, 4),
+                         "frac": round(bpl / (launch_ms * 1e-3) / HBM_PEAK, 4),
+                         "kernel": step_kernel(spl), "kernel_ms": round(launch_ms, 6),
+                         "bytes_per_launch": round(bpl),
                          "fluid_fraction_mean": round(ff, 5), "traffic": traffic,
                          "plain_copy": cp},
             "nonfinite": int(d["nonfinite"])}
 
 
-def flow_point(n=4096, steps=256, warmup=64, graph_steps=64):
+def flow_point(n=4096, steps=256, warmup=64, graph_steps=64, steps_per_launch=2):
     """The cavity workload at n x n started liquid (initial theta 0.5, above
     the liquidus), so that the flow part of the step (D2Q9 pulls, closure,
     collision) runs at nearly every node, on a state far beyond the Infinity
-    Cache: the HBM roofline of the fluid byte model (132 B per node)."""
+    Cache: the HBM roofline of the fluid byte model (132 B per node and
+    launch)."""
     import torch
     from paper_1503_08406_amd import workloads as W
     from paper_1503_08406_amd.dmrt import Solver
     case = W.cavity(nx=n, ny=n, steps=steps, T_init=0.5)
-    s = Solver(case, graph_steps=graph_steps)
+    over = dict(graph_steps=graph_steps, steps_per_launch=steps_per_launch)
+    s = Solver(case, **over)
+    spl = s.launch_steps
     s.step(warmup)
     s.sync()
     buf = s.save()
@@ -274,31 +292,38 @@ def flow_point(n=4096, steps=256, warmup=64, graph_steps=64):
     kern_ms = ev0.elapsed_time(ev1) / steps
     d = s.diag()
     s.close()
-    act, act_end = window_accounting(case, buf, steps, 16, graph_steps=graph_steps)
-    rep = repeats(case, buf, steps, n=3, graph_steps=graph_steps)
+    act, act_end = window_accounting(case, buf, steps, 16, **over)
+    rep = repeats(case, buf, steps, n=3, **over)
+    one = repeats(case, buf, steps, n=3, graph_steps=graph_steps, steps_per_launch=1)
     del buf
     cells = n * n
     ff = act / (cells * steps)
     bpl = (BYTES_FLUID * ff + BYTES_SOLID * (1 - ff)) * cells
-    med = rep["median_kernel_ms"]
+    launch_ms = rep["median_kernel_ms"] * spl
+    one_ms = one["median_kernel_ms"]
     return {"workload": "the same cavity at %dx%d started liquid (initial theta 0.5), steps "
                         "%d..%d" % (n, n, warmup, warmup + steps),
             "value": round(cells * steps / wall / 1e6, 2), "unit": "MLUPS",
-            "kernel_ms": round(kern_ms, 6),
-            "roofline": {"bound": "hbm", "achieved": round(bpl / (med * 1e-3) / 1e9, 1),
+            "kernel_ms_per_step": round(kern_ms, 6), "steps_per_launch": spl,
+            "roofline": {"bound": "hbm", "achieved": round(bpl / (launch_ms * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                         "frac": round(bpl / (med * 1e-3) / HBM_PEAK, 4),
+                         "frac": round(bpl / (launch_ms * 1e-3) / HBM_PEAK, 4),
+                         "kernel": step_kernel(spl), "kernel_ms": round(launch_ms, 6),
                          "bytes_per_launch": round(bpl), "fluid_fraction_mean": round(ff, 5),
                          "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID},
                          "repeats": rep},
+            "one_step_per_launch": {"kernel": step_kernel(1), "kernel_ms": round(one_ms, 6),
+                                    "frac": round(bpl / (one_ms * 1e-3) / HBM_PEAK, 4),
+                                    "repeats": one},
             "nonfinite": int(d["nonfinite"])}
 
 
 def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
     """The batched workload: 512 cavities of seeded uneven sizes and
     parameters (seed 4), advanced together for 10000 steps with the tuned
-    launch shape and graph replay of 64 steps; the phase mix for the byte
-    count comes from an untimed replay."""
+    launch shape (one step per launch, or two: rows 0) and graph replay of
+    64 steps; the phase mix for the byte count comes from an untimed
+    replay."""
     import torch
     from paper_1503_08406_amd import workloads as W
     from paper_1503_08406_amd.dmrt import BatchSolver
@@ -306,6 +331,7 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
     steps = steps or nsteps
     b = BatchSolver(cavs, graph_steps=64, store_hint=store_hint, **opts)
     rows, blocks, tune_ms = b.tune(trial_steps=trial_steps)
+    spl = 2 if rows == 0 else 1
     cells = b.cells
     b.sync()
     torch.cuda.synchronize()
@@ -332,6 +358,7 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
     act = sum(0.5 * (a0 + a1) * (t1 - t0_) for (t0_, a0), (t1, a1) in zip(pts, pts[1:]))
     ff = act / (cells * steps)
     bpl = (BYTES_FLUID_BATCH * ff + BYTES_SOLID_BATCH * (1 - ff)) * cells
+    launch_ms = kern_ms * spl
     mlups = cells * steps / wall / 1e6
     return {"workload": "512 convection-melting cavities (Sec. 4.3 setting), nx, ny iid in "
                         "[64, 512], Ra 10^U(4,6), Da 10^U(-5,-2), eps U(0.3,0.9), Ste U(0.1,2), "
@@ -341,11 +368,13 @@ def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
             "ms_per_step": round(wall * 1e3 / steps, 6),
             "ratio_to_single": round(mlups / single_mlups, 4),
             "launch": {"rows": rows, "blocks": blocks, "graph_steps": 64,
+                       "steps_per_launch": spl,
                        "tuner_trial_ms_per_step": round(tune_ms, 6)},
-            "roofline": {"bound": "hbm", "achieved": round(bpl / (kern_ms * 1e-3) / 1e9, 1),
+            "roofline": {"bound": "hbm", "achieved": round(bpl / (launch_ms * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                         "frac": round(bpl / (kern_ms * 1e-3) / HBM_PEAK, 4),
-                         "kernel": "k_batch_step", "kernel_ms": round(kern_ms, 6),
+                         "frac": round(bpl / (launch_ms * 1e-3) / HBM_PEAK, 4),
+                         "kernel": "k_batch_step2" if spl == 2 else "k_batch_step",
+                         "kernel_ms": round(launch_ms, 6), "kernel_ms_per_step": round(kern_ms, 6),
                          "bytes_per_launch": round(bpl), "fluid_fraction_mean": round(ff, 5),
                          "bytes_per_cell": {"fluid": BYTES_FLUID_BATCH, "solid": BYTES_SOLID_BATCH}},
             "liquid_cells_end": int(liq.sum())}
@@ -383,6 +412,17 @@ def adjoint_timing(warm=200, steps=0, record_mode=0):
 
     s.reset()
     fwd = timed(lambda: s.step(steps))
+    # the same forward run at one step per launch (context: the run before
+    # two-step launches, and what the adjoint's cost was first quoted against)
+    s1 = Solver(case, graph_steps=64, steps_per_launch=1)
+    s1.step(warm)
+    s1.reset()
+    s1.sync()
+    t0 = time.perf_counter()
+    s1.step(steps)
+    s1.sync()
+    fwd1 = (time.perf_counter() - t0) * 1e3
+    s1.close()
     s.reset()
     rec_first = timed(lambda: s.record(steps))  # captures the recording's graph
     s.reset()
@@ -401,11 +441,13 @@ def adjoint_timing(warm=200, steps=0, record_mode=0):
                         "seed 2, L = 1/2 sum((f_l - f_l*)^2 + (T - T*)^2) after %d steps" % steps,
             "record_mode": {0: "every state kept (fits in HBM)", 1: "sqrt(n) checkpoints, "
                             "segments recomputed"}[record_mode],
-            "steps": steps, "forward_ms": round(fwd, 3), "record_ms": round(rec, 3),
+            "steps": steps, "forward_ms": round(fwd, 3),
+            "forward_one_step_per_launch_ms": round(fwd1, 3), "record_ms": round(rec, 3),
             "record_first_call_ms": round(rec_first, 3),
             "adjoint_ms": round(adj, 3), "adjoint_first_call_ms": round(adj_first, 3),
             "adjoint_over_forward": round(adj / fwd, 3),
             "record_and_adjoint_over_forward": round((rec + adj) / fwd, 3),
+            "record_and_adjoint_over_forward_one_step_per_launch": round((rec + adj) / fwd1, 3),
             "loss": loss, "grad_logK_norm": float(np.linalg.norm(gk)),
             "grad_eps_norm": float(np.linalg.norm(ge)),
             "liquid_cells_end": int((F["fl"] > 0).sum())}
@@ -499,6 +541,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--block-rows", type=int, default=0, help="step-kernel block rows (0: auto)")
     ap.add_argument("--cells-per-lane", type=int, default=0, help="nodes per lane (0: auto)")
+    ap.add_argument("--steps-per-launch", type=int, default=2,
+                    help="time steps per launch of the step kernel (1 or 2)")
     ap.add_argument("--T-init", type=float, default=0.0,
                     help="initial temperature (0: solid start as in the workload; "
                          "0.5: liquid start, the flow is solved almost everywhere)")
@@ -539,7 +583,7 @@ def main():
     # one graph replay like a long one, not plain launches
     gsteps = min(args.graph_steps, args.steps // 2 * 2)
     over = dict(graph_steps=gsteps, block_rows=args.block_rows, store_hint=args.store_hint,
-                cells_per_lane=args.cells_per_lane)
+                cells_per_lane=args.cells_per_lane, steps_per_launch=args.steps_per_launch)
 
     if args.copy_probe:
         a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -554,6 +598,7 @@ def main():
     # last graph's worth of them starts at the window's buffer parity, so the
     # window replays a graph captured here
     s = Solver(case, **over)
+    spl = s.launch_steps
     pre = args.start + args.warmup
     last = gsteps if gsteps and pre >= gsteps else 0
     s.step(pre - last)
@@ -582,9 +627,13 @@ def main():
     fluid_frac = act_steps / (cells * args.steps)
     bytes_per_launch = (BYTES_FLUID * fluid_frac + BYTES_SOLID * (1 - fluid_frac)) * cells
     rep = repeats(case, buf, args.steps, **over)
+    one = None
+    if spl == 2:
+        one = repeats(case, buf, args.steps, n=3, **dict(over, steps_per_launch=1))
     del buf
-    med_ms = rep["median_kernel_ms"]
-    achieved = bytes_per_launch / (med_ms * 1e-3)
+    med_ms = rep["median_kernel_ms"]  # per step
+    launch_ms = med_ms * spl
+    achieved = bytes_per_launch / (launch_ms * 1e-3)
     # measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, two
     # phase mixes solved for bytes per solid and per liquid node), valid while
     # the step kernel source is the one that was measured
@@ -596,7 +645,7 @@ def main():
                              tr["bytes_per_cell_fluid"] * fluid_frac) * cells)
 
     cp = plain_copy(traffic or bytes_per_launch)
-    cp["frac_of_copy"] = round(cp["us"] / (med_ms * 1e3), 3)
+    cp["frac_of_copy"] = round(cp["us"] / (launch_ms * 1e3), 3)
 
     out = {
         "metric": "MLUPS (flow+thermal)",
@@ -617,22 +666,29 @@ def main():
                                % (args.n, args.n, args.T_init, t_start, t_start + args.steps),
                    "nx": args.n, "ny": args.n, "window_start": t_start,
                    "graph_steps": gsteps, "block_rows": args.block_rows,
-                   "cells_per_lane": args.cells_per_lane, "parallelism": "single GPU"},
+                   "cells_per_lane": args.cells_per_lane, "steps_per_launch": spl,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": traffic,
-                     "traffic_GBps": None if traffic is None else round(traffic / (med_ms * 1e-3) / 1e9, 1),
-                     "kernel": "k_step (flow, 4 rows, 1 node per lane)",
-                     "kernel_ms": round(med_ms, 6), "kernel_ms_timed_run": round(kern_ms, 6),
+                     "traffic_GBps": None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9, 1),
+                     "kernel": step_kernel(spl), "steps_per_launch": spl,
+                     "kernel_ms": round(launch_ms, 6), "kernel_ms_per_step": round(med_ms, 6),
+                     "kernel_ms_per_step_timed_run": round(kern_ms, 6),
                      "bytes_per_launch": round(bytes_per_launch),
                      "fluid_fraction_mean": round(fluid_frac, 5),
                      "bytes_per_cell": {"fluid": BYTES_FLUID, "solid": BYTES_SOLID},
                      "plain_copy": cp, "repeats": rep},
         "phase": {"active_cells_end": int(act_end), "front_mean_end": round(d["front_mean"], 3)},
     }
+    if one is not None:
+        one_ms = one["median_kernel_ms"]
+        out["roofline"]["one_step_per_launch"] = {
+            "kernel": step_kernel(1), "kernel_ms": round(one_ms, 6),
+            "frac": round(bytes_per_launch / (one_ms * 1e-3) / HBM_PEAK, 4), "repeats": one}
     if not args.no_hbm:
-        out["hbm_point"] = hbm_point()
-        out["flow_point"] = flow_point()
+        out["hbm_point"] = hbm_point(steps_per_launch=args.steps_per_launch)
+        out["flow_point"] = flow_point(steps_per_launch=args.steps_per_launch)
     if not args.no_batch:
         out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint)
         if "hbm_point" in out:

@@ -124,10 +124,11 @@ typedef struct {
                            The gradients are the same bits in every mode          */
     int32_t steps_per_launch; /* 0 or 1: one time step per launch; 2: two steps per
                            launch where the launch allows it (default thermal model,
-                           R1, arrays within 4 GB, block_rows 4, one node per lane):
+                           R1, arrays within 4 GB, block_rows 4, one node per lane;
+                           otherwise, and for a last odd step, one per launch):
                            the intermediate state stays in LDS, so a node update
                            moves half the bytes.  The results are the same bits;
-                           default 1                                              */
+                           default 2                                              */
 } dmrt_opts;
 
 /* Lattice constants derived from the dimensionless inputs (Sec. 4.3). */
@@ -215,6 +216,11 @@ int dmrt_diag_noalloc(dmrt_t *h, dmrt_diag_t *out);
 /* Lattice constants the handle runs with. */
 int dmrt_get_derived(const dmrt_t *h, dmrt_derived *out);
 
+/* Time steps one launch of the step kernel advances: 2 where two steps per
+ * launch are in effect (steps_per_launch 2 and a configuration that allows
+ * it), else 1; a negative DMRT_* code for a null handle. */
+int32_t dmrt_launch_steps(const dmrt_t *h);
+
 /* Enthalpy-iteration statistics of the last step taken with counting on:
  * dmrt_step_counted(h, n) runs n steps and accumulates per-cell iteration
  * counts; max_it and mean_it (over cells and steps) are returned. */
@@ -286,8 +292,9 @@ typedef struct {
 /* Create a batch of ncav >= 1 cavities on the current HIP device, every one
  * initialised as dmrt_create does.  opts (may be NULL) applies to all
  * cavities; its graph_steps and check_every act on the batch, block_rows
- * picks the first launch shape (see dmrt_batch_set_launch) and
- * cells_per_lane is ignored.  DMRT_EINVAL names the first bad cavity. */
+ * picks the launch shape of the one-step kernel (see dmrt_batch_set_launch),
+ * steps_per_launch 2 (the default) starts the batch on the two-step kernel
+ * and cells_per_lane is ignored.  DMRT_EINVAL names the first bad cavity. */
 int dmrt_batch_create(int32_t ncav, const dmrt_cavity *cav, const dmrt_opts *opts,
                       dmrt_batch_t **out);
 
@@ -302,18 +309,25 @@ int dmrt_batch_fields(dmrt_batch_t *b, int32_t i, float *T, float *ux, float *uy
  * and g; either array (ncav entries) may be NULL. */
 int dmrt_batch_check(dmrt_batch_t *b, int64_t *liquid, int64_t *nonfinite);
 
-/* Launch shape of the batched step: rows of a 64-wide tile (4 or 8) and the
- * number of blocks (a multiple of 8; 0 = as many as the device holds at
- * once).  The shape changes speed only, never results. */
+/* Launch shape of the batched step.  rows 4 or 8: one step per launch,
+ * tiles of 64 x rows nodes, and the number of blocks (a multiple of 8; 0 =
+ * as many as the device holds at once).  rows 0 (only for a batch created
+ * with steps_per_launch 2; blocks is ignored): two steps per launch, tiles
+ * of 62 x 6 nodes, one block per tile; a last odd step of dmrt_batch_step
+ * then runs on the one-step shape set last.  dmrt_batch_get_launch gives
+ * rows 0 and the two-step kernel's block count in that case.  The shape
+ * changes speed only, never results. */
 int dmrt_batch_set_launch(dmrt_batch_t *b, int32_t rows, int32_t blocks);
 int dmrt_batch_get_launch(const dmrt_batch_t *b, int32_t *rows, int32_t *blocks);
 
 /* Autotuner of the launch shape.  For every candidate (rows 4 and 8; as
- * many blocks as the device holds at once, twice that, one block per tile)
- * run trial_steps >= 1 untimed and then trial_steps timed steps from a copy
- * of the current state; keep the fastest (dmrt_batch_set_launch) and
- * restore the state, so results and the time counter are unchanged.  Any
- * output pointer may be NULL; ms_per_step is the winner's mean step time. */
+ * many blocks as the device holds at once, twice that, one block per tile;
+ * and rows 0, two steps per launch, where the batch allows it) run
+ * trial_steps >= 1 untimed and then trial_steps timed steps from a copy of
+ * the current state; keep the fastest (dmrt_batch_set_launch; the fastest
+ * one-step shape stays the shape of single launches) and restore the state,
+ * so results and the time counter are unchanged.  Any output pointer may be
+ * NULL; ms_per_step is the winner's mean step time. */
 int dmrt_batch_tune(dmrt_batch_t *b, int32_t trial_steps, int32_t *rows, int32_t *blocks,
                     double *ms_per_step);
 

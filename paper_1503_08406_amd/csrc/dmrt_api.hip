@@ -118,6 +118,7 @@ struct dmrt {
     bool adj_flow = false;
     int record_mode = 0;
     bool rec_all = false;  // every state of the recorded run kept (no recomputation)
+    int rec_flip = 0;      // buffer parity change of a recorded run (checkpoint mode)
     hipGraphExec_t rec_graph[2]{};  // the recording's launches from buffer parity 0 / 1
     bool rec_graph_flow = false;
     // latent source at the pre-stream site: T*, two f_l iterates, sweep flags
@@ -521,6 +522,32 @@ void drop_recording(dmrt* h)
     h->rec_n = h->rec_S = h->rec_cap = 0;
 }
 
+dmrtk::StepBufs ring_bufs(const dmrt* h, const float* a, float* b);
+
+// Steps from ring state a at slot k into the following slots up to slot
+// end: two per launch where the handle runs two steps per launch (the state
+// between them stored too), else one.
+hipError_t ring_steps(dmrt* h, const float* a, int64_t k, int64_t end, float* ring, size_t sb)
+{
+    const bool two = use_two_step(h);
+    while (k < end) {
+        hipError_t e;
+        if (two && k + 2 <= end) {
+            const dmrtk::StepBufs mid = ring_bufs(h, a, ring + (size_t)(k + 1) * sb);
+            e = dmrtk::launch_step2(h->G, h->P, ring_bufs(h, a, ring + (size_t)(k + 2) * sb), h->flow,
+                                    h->stream, &mid);
+            k += 2;
+        } else {
+            e = dmrtk::launch_step(h->G, h->P, ring_bufs(h, a, ring + (size_t)(k + 1) * sb), h->flow,
+                                   false, h->stream);
+            k += 1;
+        }
+        if (e != hipSuccess) return e;
+        a = ring + (size_t)k * sb;
+    }
+    return hipSuccess;
+}
+
 // Enqueue the reversed pass over a recorded run of n steps: per segment,
 // last segment first, recompute its states into the ring (the first read
 // from its checkpoint), then one adjoint launch per step, last step first;
@@ -544,26 +571,8 @@ int enqueue_adjoint(dmrt* h)
             hipError_t e = dmrtk::launch_copy(h->flnext, h->ring + sb + (fq + 5) * pl, pl, h->stream);
             if (e != hipSuccess) return fail(DMRT_EDEVICE, "copy launch: %s", hipGetErrorString(e));
         }
-        for (int64_t j = 0; j < len && !h->rec_all; ++j) {
-            const float* a = state(j);
-            float* b = h->ring + (size_t)(j + 1) * sb;
-            dmrtk::StepBufs B;
-            B.fin = a;
-            B.fout = b;
-            B.gin = a + fq * pl;
-            B.gout = b + fq * pl;
-            B.flin = a + (fq + 5) * pl;
-            B.flout = b + (fq + 5) * pl;
-            B.ux = b + (fq + 6) * pl;
-            B.uy = b + (fq + 7) * pl;
-            B.uin = a + (fq + 6) * pl;
-            B.eps = h->eps;
-            B.Ac = h->Ac;
-            B.Bc = h->Bc;
-            B.it_sum = B.it_max = nullptr;
-            B.r2f = nullptr;
-            B.r2_its = 0;
-            hipError_t e = dmrtk::launch_step(G, h->P, B, h->flow, false, h->stream);
+        if (!h->rec_all) {
+            hipError_t e = ring_steps(h, ck, 0, len, h->ring, sb);
             if (e != hipSuccess) return fail(DMRT_EDEVICE, "recompute launch: %s", hipGetErrorString(e));
         }
         for (int64_t j = len - 1; j >= 0; --j, ++r) {
@@ -641,21 +650,23 @@ int enqueue_record(dmrt* h, int p)
     const int64_t n = h->rec_n, S = h->rec_S;
     if (h->rec_all) {
         HIPCHK(state_copy(h, p, h->ckpt, true));
-        for (int64_t k = 0; k < n; ++k) {
-            const float* a = k == 0 ? h->ckpt : h->ring + (size_t)k * sb;
-            HIPCHK(dmrtk::launch_step(h->G, h->P, ring_bufs(h, a, h->ring + (size_t)(k + 1) * sb),
-                                      h->flow, false, h->stream));
-        }
+        HIPCHK(ring_steps(h, h->ckpt, 0, n, h->ring, sb));
         HIPCHK(state_copy(h, p, h->ring + (size_t)n * sb, false));
         return DMRT_OK;
     }
     const int save = h->cur;
     h->cur = p;
+    const bool two = use_two_step(h);
+    int launches = 0;
     for (int64_t c = 0, k = 0; k < n; ++c) {
         hipError_t e = state_copy(h, h->cur, h->ckpt + (size_t)c * sb, true);
-        for (int64_t j = 0; j < S && k < n && e == hipSuccess; ++j, ++k) {
-            e = enqueue_step(h, false);
+        for (int64_t j = 0; j < S && k < n && e == hipSuccess;) {
+            const int st = (two && j + 2 <= S && k + 2 <= n) ? 2 : 1;
+            e = st == 2 ? enqueue_step2(h) : enqueue_step(h, false);
             h->cur = 1 - h->cur;
+            j += st;
+            k += st;
+            ++launches;
         }
         if (e != hipSuccess) {
             h->cur = save;
@@ -663,6 +674,7 @@ int enqueue_record(dmrt* h, int p)
         }
     }
     h->cur = save;
+    h->rec_flip = launches & 1;
     return DMRT_OK;
 }
 
@@ -732,7 +744,7 @@ void dmrt_opts_default(dmrt_opts* o)
     o->ks_ratio = 1.0;
     o->km_ratio = 1.0;
     o->record_mode = 0;
-    o->steps_per_launch = 1;
+    o->steps_per_launch = 2;
 }
 
 int dmrt_derive(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
@@ -1037,6 +1049,12 @@ int dmrt_get_derived(const dmrt_t* h, dmrt_derived* out)
     return DMRT_OK;
 }
 
+int32_t dmrt_launch_steps(const dmrt_t* h)
+{
+    if (!h) return fail(DMRT_EINVAL, "null handle");
+    return use_two_step(h) ? 2 : 1;
+}
+
 int64_t dmrt_state_bytes(const dmrt_t* h)
 {
     if (!h) return fail(DMRT_EINVAL, "null handle");
@@ -1183,7 +1201,7 @@ int dmrt_record(dmrt_t* h, int64_t n)
             return rc;
         }
     }
-    if (!keep_all && (n & 1)) h->cur = 1 - h->cur;
+    if (!keep_all) h->cur ^= h->rec_flip;  // every-state mode ends back at parity p
     h->t += n;
     if (h->check_every > 0) return check_finite(h);
     return DMRT_OK;
@@ -1293,17 +1311,24 @@ struct dmrt_batch {
     int cur = 0;
     int64_t t = 0;
     int check_every = 0, graph_steps = 0;
-    int rows = 4, blocks = 0, launch_blocks = 0;
+    int rows = 4, blocks = 0, launch_blocks = 0;  // one-step launch shape
     int store = 0;  // cache policy of the state stores
     int die[dmrtk::NXCD + 1]{};
     size_t f_len = 0, g_len = 0, fl_len = 0, u_len = 0;  // arena lengths in floats
     char* base = nullptr;
-    float *f[2]{}, *g[2]{}, *fl[2]{}, *u = nullptr;
+    float *f[2]{}, *g[2]{}, *fl[2]{}, *u[2]{};  // u[p]: the velocity of state parity p
     dmrtk::Cavity* dcav = nullptr;
     int4* dtiles = nullptr;
     size_t tiles_cap = 0;
+    // two steps per launch: allowed (steps_per_launch 2), in effect, and its
+    // tile list cut into die parts, launched with one block per tile
+    bool two_ok = false, two = false;
+    int4* dtiles2 = nullptr;
+    int die2[dmrtk::NXCD + 1]{};
+    int blocks2 = 0;
     long long* partials = nullptr;
     hipGraphExec_t graph[2]{};
+    int graph_flip[2]{};  // buffer parity changes of a replay of graph[p]
 };
 
 namespace {
@@ -1317,6 +1342,52 @@ void drop_graphs(dmrt_batch* b)
             (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
+}
+
+// Cut a tile list (node counts w) into NXCD contiguous parts of about equal
+// node count: die d takes tiles [die[d], die[d + 1]).  Returns the largest
+// part's tile count.
+int cut_dies(const std::vector<long long>& w, int* die)
+{
+    const int nt = (int)w.size();
+    long long total = 0;
+    for (long long v : w) total += v;
+    int d = 1;
+    long long acc = 0;
+    die[0] = 0;
+    for (int k = 0; k < nt && d < dmrtk::NXCD; ++k) {
+        acc += w[k];
+        while (d < dmrtk::NXCD && acc * dmrtk::NXCD >= total * d) die[d++] = k + 1;
+    }
+    while (d <= dmrtk::NXCD) die[d++] = nt;
+    int most = 0;
+    for (int k = 0; k < dmrtk::NXCD; ++k) most = std::max(most, die[k + 1] - die[k]);
+    return most;
+}
+
+// Tile list of the two-step kernel: tiles of T2_W x T2_ROWS nodes, row-major
+// inside each cavity, cavity by cavity; one block per tile.
+int batch_layout2(dmrt_batch* b)
+{
+    int tw = 0, th = 0;
+    dmrtk::batch_step2_tile(&tw, &th);
+    std::vector<int4> tl;
+    std::vector<long long> w;
+    for (int c = 0; c < b->ncav; ++c) {
+        const Geom& G = b->cav[c].G;
+        for (int y0 = 0; y0 < G.ny; y0 += th)
+            for (int x0 = 0; x0 < G.nx; x0 += tw) {
+                tl.push_back(make_int4(c, x0, y0, 0));
+                w.push_back((long long)std::min(tw, G.nx - x0) * std::min(th, G.ny - y0));
+            }
+    }
+    const int most = cut_dies(w, b->die2);
+    b->blocks2 = dmrtk::NXCD * std::max(1, most);
+    HIPCHK(hipMalloc(&b->dtiles2, tl.size() * sizeof(int4)));
+    HIPCHK(hipMemcpyAsync(b->dtiles2, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return DMRT_OK;
 }
 
 // Tile list for tiles of 64 x rows nodes, cut into one contiguous part per
@@ -1345,18 +1416,7 @@ int batch_layout(dmrt_batch* b, int rows, int blocks)
         }
     }
     const int nt = (int)tl.size();
-    long long total = 0;
-    for (long long v : w) total += v;
-    int d = 1;
-    long long acc = 0;
-    b->die[0] = 0;
-    for (int k = 0; k < nt && d < dmrtk::NXCD; ++k) {
-        acc += w[k];
-        while (d < dmrtk::NXCD && acc * dmrtk::NXCD >= total * d) b->die[d++] = k + 1;
-    }
-    while (d <= dmrtk::NXCD) b->die[d++] = nt;
-    int most = 0;
-    for (int k = 0; k < dmrtk::NXCD; ++k) most = std::max(most, b->die[k + 1] - b->die[k]);
+    const int most = cut_dies(w, b->die);
     int nb = blocks;
     if (nb == 0) {
         int ncu = 0;
@@ -1382,43 +1442,68 @@ int batch_layout(dmrt_batch* b, int rows, int blocks)
     return DMRT_OK;
 }
 
-dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p)
+// Arguments of a launch from state parity p: of the one-step kernel, or of
+// the two-step kernel (its tile list) when two is set.
+dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p, bool two = false)
 {
     dmrtk::BatchArgs a;
     a.cav = b->dcav;
-    a.tiles = b->dtiles;
-    for (int k = 0; k <= dmrtk::NXCD; ++k) a.die[k] = b->die[k];
+    a.tiles = two ? b->dtiles2 : b->dtiles;
+    for (int k = 0; k <= dmrtk::NXCD; ++k) a.die[k] = two ? b->die2[k] : b->die[k];
     a.fin = b->f[p];
     a.fout = b->f[1 - p];
     a.gin = b->g[p];
     a.gout = b->g[1 - p];
     a.flin = b->fl[p];
     a.flout = b->fl[1 - p];
-    a.u = b->u;
+    a.uin = b->u[p];
+    a.uout = b->u[1 - p];
     a.store = b->store;
     return a;
+}
+
+// One launch from parity b->cur: two steps (two-step kernel in effect and
+// at least two steps wanted) or one.  Flips the parity; returns the steps.
+hipError_t batch_launch(dmrt_batch* b, int64_t n, int* steps)
+{
+    const bool two = b->two && n >= 2;
+    hipError_t e = two ? dmrtk::launch_batch_step2(batch_args(b, b->cur, true), b->blocks2, b->stream)
+                       : dmrtk::launch_batch_step(batch_args(b, b->cur), b->rows, b->launch_blocks,
+                                                  b->stream);
+    b->cur = 1 - b->cur;
+    *steps = two ? 2 : 1;
+    return e;
 }
 
 int batch_graph(dmrt_batch* b, int p)
 {
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    int q = p;
-    for (int k = 0; k < b->graph_steps; ++k) {
-        hipError_t e = dmrtk::launch_batch_step(batch_args(b, q), b->rows, b->launch_blocks,
-                                                b->stream);
-        q = 1 - q;
+    const int save = b->cur;
+    b->cur = p;
+    int launches = 0;
+    for (int k = 0; k < b->graph_steps;) {
+        int st = 1;
+        hipError_t e = batch_launch(b, b->graph_steps - k, &st);
+        k += st;
+        ++launches;
         if (e != hipSuccess) {
+            b->cur = save;
             hipGraph_t gdrop = nullptr;
             (void)hipStreamEndCapture(b->stream, &gdrop);
             if (gdrop) (void)hipGraphDestroy(gdrop);
             return fail(DMRT_EDEVICE, "launch during capture: %s", hipGetErrorString(e));
         }
     }
+    b->cur = save;
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamEndCapture(b->stream, &graph));
     hipError_t e = hipGraphInstantiate(&b->graph[p], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        b->graph[p] = nullptr;
+        return fail(DMRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    b->graph_flip[p] = launches & 1;
     return DMRT_OK;
 }
 
@@ -1466,11 +1551,12 @@ int batch_step_impl(dmrt_batch* b, int64_t n)
                 if (rc) return rc;
             }
             HIPCHK(hipGraphLaunch(b->graph[p], b->stream));
-            chunk = b->graph_steps;  // even: parity unchanged
+            b->cur = p ^ b->graph_flip[p];
+            chunk = b->graph_steps;
         } else {
-            HIPCHK(dmrtk::launch_batch_step(batch_args(b, b->cur), b->rows, b->launch_blocks,
-                                            b->stream));
-            b->cur = 1 - b->cur;
+            int st = 1;
+            HIPCHK(batch_launch(b, n, &st));
+            chunk = st;
         }
         b->t += chunk;
         n -= chunk;
@@ -1556,8 +1642,8 @@ int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opt
     const size_t bytes_fl = align256(b->fl_len * 4), bytes_u = align256(b->u_len * 4);
     const size_t bytes_c = align256((size_t)ncav * sizeof(dmrtk::Cavity));
     const size_t bytes_p = align256((size_t)2 * kCountBlocks * ncav * sizeof(long long));
-    const size_t total = 2 * (bytes_f + bytes_g + bytes_fl) + bytes_u + bytes_c + bytes_p;
-    b->store = store_policy(o.store_hint, 2 * (bytes_f + bytes_g + bytes_fl) + bytes_u);
+    const size_t total = 2 * (bytes_f + bytes_g + bytes_fl + bytes_u) + bytes_c + bytes_p;
+    b->store = store_policy(o.store_hint, 2 * (bytes_f + bytes_g + bytes_fl + bytes_u));
     e = hipMalloc(&b->base, total);
     if (e != hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? DMRT_ENOMEM : DMRT_EDEVICE,
@@ -1572,8 +1658,8 @@ int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opt
         b->f[k] = (float*)take(bytes_f);
         b->g[k] = (float*)take(bytes_g);
         b->fl[k] = (float*)take(bytes_fl);
+        b->u[k] = (float*)take(bytes_u);
     }
-    b->u = (float*)take(bytes_u);
     b->dcav = (dmrtk::Cavity*)take(bytes_c);
     b->partials = (long long*)take(bytes_p);
     e = hipMemsetAsync(b->base, 0, total, b->stream);
@@ -1585,14 +1671,17 @@ int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opt
     for (int c = 0; c < ncav; ++c) {
         const dmrtk::Cavity& C = b->cav[c];
         e = dmrtk::launch_load_state(C.G, C.P, nullptr, nullptr, nullptr, b->f[0] + C.f_off,
-                                     b->g[0] + C.g_off, b->fl[0] + C.fl_off, b->u + C.u_off,
-                                     b->u + C.u_off + C.G.plane, nullptr, nullptr, nullptr, true,
+                                     b->g[0] + C.g_off, b->fl[0] + C.fl_off, b->u[0] + C.u_off,
+                                     b->u[0] + C.u_off + C.G.plane, nullptr, nullptr, nullptr, true,
                                      b->stream, C.eps, C.Ac, C.Bc);
         if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "initial state: %s", hipGetErrorString(e)));
     }
     e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "initial state: %s", hipGetErrorString(e)));
     if ((rc = batch_layout(b, o.block_rows ? o.block_rows : 4, 0))) return bail(rc);
+    b->two_ok = o.steps_per_launch == 2;
+    if (b->two_ok && (rc = batch_layout2(b))) return bail(rc);
+    b->two = b->two_ok;
     *out = b;
     return DMRT_OK;
 }
@@ -1615,8 +1704,9 @@ int dmrt_batch_fields(dmrt_batch_t* b, int32_t i, float* T, float* ux, float* uy
     float* s = nullptr;
     HIPCHK(hipMalloc(&s, 4 * ncell * sizeof(float)));
     const int a = b->cur;
-    hipError_t e = dmrtk::launch_fields(C.G, b->g[a] + C.g_off, b->fl[a] + C.fl_off, b->u + C.u_off,
-                                        b->u + C.u_off + C.G.plane, true, s, b->stream);
+    hipError_t e = dmrtk::launch_fields(C.G, b->g[a] + C.g_off, b->fl[a] + C.fl_off,
+                                        b->u[a] + C.u_off, b->u[a] + C.u_off + C.G.plane, true, s,
+                                        b->stream);
     float* dst[4] = {T, ux, uy, fl};
     for (int k = 0; k < 4 && e == hipSuccess; ++k)
         if (dst[k]) e = hipMemcpyAsync(dst[k], s + k * ncell, ncell * 4, hipMemcpyDefault, b->stream);
@@ -1643,19 +1733,28 @@ int dmrt_batch_check(dmrt_batch_t* b, int64_t* liquid, int64_t* nonfinite)
 int dmrt_batch_set_launch(dmrt_batch_t* b, int32_t rows, int32_t blocks)
 {
     if (!b) return fail(DMRT_EINVAL, "null handle");
-    if (rows != 4 && rows != 8) return fail(DMRT_EINVAL, "rows must be 4 or 8");
+    if (rows == 0) {
+        if (!b->two_ok) return fail(DMRT_EINVAL, "rows 0 (two steps per launch) needs steps_per_launch 2");
+        HIPCHK(hipSetDevice(b->dev));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        if (!b->two) drop_graphs(b);
+        b->two = true;
+        return DMRT_OK;
+    }
+    if (rows != 4 && rows != 8) return fail(DMRT_EINVAL, "rows must be 0, 4 or 8");
     if (blocks < 0 || blocks % dmrtk::NXCD)
         return fail(DMRT_EINVAL, "blocks must be 0 or a positive multiple of 8");
     HIPCHK(hipSetDevice(b->dev));
     HIPCHK(hipStreamSynchronize(b->stream));
+    b->two = false;
     return batch_layout(b, rows, blocks);
 }
 
 int dmrt_batch_get_launch(const dmrt_batch_t* b, int32_t* rows, int32_t* blocks)
 {
     if (!b) return fail(DMRT_EINVAL, "null handle");
-    if (rows) *rows = b->rows;
-    if (blocks) *blocks = b->launch_blocks;
+    if (rows) *rows = b->two ? 0 : b->rows;
+    if (blocks) *blocks = b->two ? b->blocks2 : b->launch_blocks;
     return DMRT_OK;
 }
 
@@ -1665,7 +1764,9 @@ int dmrt_batch_tune(dmrt_batch_t* b, int32_t trial_steps, int32_t* rows, int32_t
     if (!b) return fail(DMRT_EINVAL, "null handle");
     if (trial_steps < 1) return fail(DMRT_EINVAL, "trial_steps must be >= 1");
     HIPCHK(hipSetDevice(b->dev));
-    // candidates: tile rows x (resident blocks, twice that, one block per tile)
+    // candidates: tile rows x (resident blocks, twice that, one block per
+    // tile) of the one-step kernel, and the two-step kernel (rows 0) where
+    // it is allowed
     int ncu = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->dev));
     struct Cand { int rows, blocks; };
@@ -1674,6 +1775,7 @@ int dmrt_batch_tune(dmrt_batch_t* b, int32_t trial_steps, int32_t* rows, int32_t
         const int res = dmrtk::batch_blocks_per_cu(r) * ncu / dmrtk::NXCD * dmrtk::NXCD;
         for (int nb : {res, 2 * res, 1 << 30}) cands.push_back({r, nb / dmrtk::NXCD * dmrtk::NXCD});
     }
+    if (b->two_ok) cands.push_back({0, 0});
     // snapshot of the current state (the trial steps overwrite both buffers)
     const int a = b->cur;
     const size_t nf = b->f_len * 4, ng = b->g_len * 4, nfl = b->fl_len * 4, nu = b->u_len * 4;
@@ -1686,7 +1788,7 @@ int dmrt_batch_tune(dmrt_batch_t* b, int32_t trial_steps, int32_t* rows, int32_t
         char* q = snap;
         hipError_t r = hipSuccess;
         const std::pair<char*, size_t> parts[4] = {{(char*)b->f[a], nf}, {(char*)b->g[a], ng},
-                                                   {(char*)b->fl[a], nfl}, {(char*)b->u, nu}};
+                                                   {(char*)b->fl[a], nfl}, {(char*)b->u[a], nu}};
         for (const auto& pr : parts) {
             if (r == hipSuccess)
                 r = restore ? hipMemcpyAsync(pr.first, q, pr.second, hipMemcpyDeviceToDevice, b->stream)
@@ -1697,22 +1799,25 @@ int dmrt_batch_tune(dmrt_batch_t* b, int32_t trial_steps, int32_t* rows, int32_t
     };
     if (e == hipSuccess) e = save(false);
     const int keep_rows = b->rows, keep_blocks = b->blocks;
-    int best = -1, rc = DMRT_OK;
-    float best_ms = 0;
+    const bool keep_two = b->two;
+    int best = -1, best1 = -1, rc = DMRT_OK;  // best1: fastest one-step shape
+    float best_ms = 0, best1_ms = 0;
+    auto run = [&](int steps) {
+        for (int s = 0; s < steps && e == hipSuccess;) {
+            int st = 1;
+            e = batch_launch(b, steps - s, &st);
+            s += st;
+        }
+    };
     for (size_t k = 0; k < cands.size() && e == hipSuccess && rc == DMRT_OK; ++k) {
-        if ((rc = batch_layout(b, cands[k].rows, cands[k].blocks))) break;
+        b->two = cands[k].rows == 0;
+        if (!b->two && (rc = batch_layout(b, cands[k].rows, cands[k].blocks))) break;
         b->cur = a;
         // trial_steps untimed steps (the state moves past its first steps,
         // which are not representative), then trial_steps timed ones
-        for (int s = 0; s < trial_steps && e == hipSuccess; ++s) {
-            e = dmrtk::launch_batch_step(batch_args(b, b->cur), b->rows, b->launch_blocks, b->stream);
-            b->cur = 1 - b->cur;
-        }
+        run(trial_steps);
         if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int s = 0; s < trial_steps && e == hipSuccess; ++s) {
-            e = dmrtk::launch_batch_step(batch_args(b, b->cur), b->rows, b->launch_blocks, b->stream);
-            b->cur = 1 - b->cur;
-        }
+        run(trial_steps);
         if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0;
@@ -1720,6 +1825,10 @@ int dmrt_batch_tune(dmrt_batch_t* b, int32_t trial_steps, int32_t* rows, int32_t
         if (e == hipSuccess && (best < 0 || ms < best_ms)) {
             best = (int)k;
             best_ms = ms;
+        }
+        if (e == hipSuccess && !b->two && (best1 < 0 || ms < best1_ms)) {
+            best1 = (int)k;
+            best1_ms = ms;
         }
         b->cur = a;
         if (e == hipSuccess) e = save(true);
@@ -1730,13 +1839,15 @@ int dmrt_batch_tune(dmrt_batch_t* b, int32_t trial_steps, int32_t* rows, int32_t
     (void)hipFree(snap);
     b->cur = a;
     if (e != hipSuccess) rc = fail(DMRT_EDEVICE, "tune: %s", hipGetErrorString(e));
-    if (rc || best < 0) {
+    if (rc || best < 0 || best1 < 0) {
+        b->two = keep_two;
         (void)batch_layout(b, keep_rows, keep_blocks);
         return rc ? rc : fail(DMRT_EDEVICE, "tune: no candidate ran");
     }
-    if ((rc = batch_layout(b, cands[best].rows, cands[best].blocks))) return rc;
-    if (rows) *rows = b->rows;
-    if (blocks) *blocks = b->launch_blocks;
+    // the fastest one-step shape stays the shape of single launches
+    if ((rc = batch_layout(b, cands[best1].rows, cands[best1].blocks))) return rc;
+    b->two = cands[best].rows == 0;
+    if ((rc = dmrt_batch_get_launch(b, rows, blocks))) return rc;
     if (ms_per_step) *ms_per_step = best_ms / trial_steps;
     return DMRT_OK;
 }
@@ -1768,6 +1879,7 @@ void dmrt_batch_destroy(dmrt_batch_t* b)
     if (b->base) (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
     if (b->dtiles) (void)hipFree(b->dtiles);
+    if (b->dtiles2) (void)hipFree(b->dtiles2);
     if (b->base) (void)hipFree(b->base);
     delete b;
 }

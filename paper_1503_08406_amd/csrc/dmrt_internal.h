@@ -90,7 +90,10 @@ hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flo
 // (u double-buffered: B.uin holds u^k).  For the default thermal model,
 // 32-bit offsets, the 4-row launch shape and one node per lane.
 bool step2_supported(const Geom& G, const Phys& P);
-hipError_t launch_step2(const Geom& G, const Phys& P, const StepBufs& B, bool flow, hipStream_t s);
+// Two steps per launch: B's inputs hold state k, its outputs receive state
+// k+2; with mid, its outputs receive state k+1 as well.
+hipError_t launch_step2(const Geom& G, const Phys& P, const StepBufs& B, bool flow, hipStream_t s,
+                        const StepBufs* mid = nullptr);
 
 // One step with the latent source at the pre-stream site (R2): T* of every
 // node (ts), at most P.fl_maxit Jacobi sweeps of f_l over the lattice
@@ -128,13 +131,19 @@ struct BatchArgs {
     float* gout;
     const float* flin;
     float* flout;
-    float* u;
+    const float* uin;  // u^k (two planes per cavity at its u_off)
+    float* uout;       // u^{k+1}, or u^{k+2} after two steps
     int store;  // cache policy of the state stores (ST_*)
 };
 
 // Persistent batched step: `blocks` blocks (a multiple of 8) of 64 x rows
 // lanes; the blocks of die d walk that die's part of the tile list.
 hipError_t launch_batch_step(const BatchArgs& a, int rows, int blocks, hipStream_t s);
+// Two steps per launch over a list of two-step tiles (a.tiles, a.die): one
+// block per tile, `blocks` = 8 x the largest part of a die.
+hipError_t launch_batch_step2(const BatchArgs& a, int blocks, hipStream_t s);
+// Two-step tiles: pass-B width and rows; returns the waves of a block.
+int batch_step2_tile(int* width, int* rows);
 // Blocks of 64 x rows lanes that fit on one compute unit at once.
 int batch_blocks_per_cu(int rows);
 // Per-cavity partial counts of liquid nodes (f_l > 0) and of non-finite f_l

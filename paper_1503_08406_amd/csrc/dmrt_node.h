@@ -323,12 +323,14 @@ __device__ __forceinline__ float rho_dev(const float (&d)[9])
 // melted in this step restarts at rest (flow_gather_restart).  Then the
 // velocity closure and the MRT collision with forcing.  Every load of the
 // node is issued in one batch; values are selected afterwards, so no load
-// waits behind a data-dependent branch.
+// waits behind a data-dependent branch.  The node's drag coefficients are
+// handed back for a second step of the same node.
 template <class IO, bool USTAT>
 __device__ __forceinline__ void node_flow_core(const Geom& G, const Phys& P, const Arrays<IO>& A,
                                                int x, int y, float flk, float fl1, float T1,
                                                float eps, float (&d)[9], float& ux, float& uy,
-                                               typename IO::off_t& o_out)
+                                               typename IO::off_t& o_out, float& Ac_out,
+                                               float& Bc_out)
 {
     using off_t = typename IO::off_t;
     const off_t pb = A.pb;
@@ -346,6 +348,8 @@ __device__ __forceinline__ void node_flow_core(const Geom& G, const Phys& P, con
     const float Ac = USTAT ? A.Ac_u : A.stat.ld(o, pb);
     const float Bc = USTAT ? A.Bc_u : A.stat.ld(o, 2 * pb);
     o_out = o;
+    Ac_out = Ac;
+    Bc_out = Bc;
 
     if (flk > 0.0f) {
         float v[27];  // neighbour f_l (0-7), pulls (8-16), own f+_1..8 (17-24), u^k
@@ -396,9 +400,9 @@ __device__ __forceinline__ void node_flow(const Geom& G, const Phys& P, const Ar
 {
     using off_t = typename IO::off_t;
     const off_t pb = A.pb;
-    float d[9];
+    float d[9], Ac, Bc;
     off_t o;
-    node_flow_core<IO, USTAT>(G, P, A, x, y, flk, fl1, T1, eps, d, ux, uy, o);
+    node_flow_core<IO, USTAT>(G, P, A, x, y, flk, fl1, T1, eps, d, ux, uy, o, Ac, Bc);
 #pragma unroll
     for (int i = 0; i < 9; ++i) A.fout.st(o, (off_t)i * pb, d[i]);
     A.fout.st(o, 9 * pb, rho_dev(d));

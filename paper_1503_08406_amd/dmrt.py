@@ -99,6 +99,7 @@ def _load():
         "dmrt_get_derived": (C.c_int, [P, C.POINTER(Derived)]),
         "dmrt_step_counted": (C.c_int, [P, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "dmrt_state_bytes": (C.c_int64, [P]),
+        "dmrt_launch_steps": (C.c_int32, [P]),
         "dmrt_save": (C.c_int, [P, VP, C.c_size_t]),
         "dmrt_load": (C.c_int, [P, VP, C.c_size_t]),
         "dmrt_set_porous": (C.c_int, [P, VP, VP, VP]),
@@ -220,6 +221,14 @@ class Solver:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def launch_steps(self):
+        """Time steps one launch of the step kernel advances (1 or 2)."""
+        n = _lib.dmrt_launch_steps(self._h)
+        if n < 0:
+            _check(n)
+        return n
 
     def close(self):
         if getattr(self, "_h", None):
@@ -345,7 +354,8 @@ class Solver:
 
 
 class BatchSolver:
-    """Many independent cavities advanced together by one launch per step.
+    """Many independent cavities advanced together, one or two steps per
+    launch (steps_per_launch, default 2).
     `cavities` is a list of dicts with nx, ny, bc_kind, T_wall, eps (a
     scalar), Ra, Da, Pr, Ste and optionally H; keyword arguments are solver
     options shared by all cavities."""

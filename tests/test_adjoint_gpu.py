@@ -110,24 +110,26 @@ def test_adjoint_matches_oracle_adjoint(kind):
 
 def test_record_modes_give_the_same_gradients_and_state():
     """Keeping every state of the run (no recomputation) and keeping sqrt(n)
-    checkpoints (segments recomputed) give the same gradients bit for bit;
-    the recorded run ends at the state dmrt_step reaches, and a second
-    recording (graph replay) repeats the first."""
+    checkpoints (segments recomputed), each recorded (and recomputed) with one
+    or two steps per launch, give the same gradients bit for bit; the
+    recorded run ends at the state dmrt_step reaches, and a second recording
+    (graph replay) repeats the first."""
     from paper_1503_08406_amd.dmrt import Solver
     case, steps, wT, wf = _case("liquid")
     steps += 3  # not a square, odd
-    ref = Solver(case, fl_tol=1e-7)
+    ref = Solver(case, fl_tol=1e-7, steps_per_launch=1)
     ref.step(steps)
     Fr = ref.fields()
     out = []
-    for mode in (2, 1):
-        s = Solver(case, fl_tol=1e-7, record_mode=mode)
+    for mode, spl in ((2, 2), (1, 2), (2, 1), (1, 1)):
+        s = Solver(case, fl_tol=1e-7, record_mode=mode, steps_per_launch=spl)
+        assert s.launch_steps == spl
         for rep in range(2):
             s.reset()
             s.record(steps)
             F = s.fields()
             for k in F:
-                assert np.array_equal(F[k], Fr[k]), (mode, rep, k)
+                assert np.array_equal(F[k], Fr[k]), (mode, spl, rep, k)
             assert s.time == steps * (rep + 1)
             g = s.adjoint(wT, wf)
             if rep:
@@ -135,8 +137,9 @@ def test_record_modes_give_the_same_gradients_and_state():
             out.append(g)
         s.close()
     _say("record modes: max |dL/deps| %.3e" % float(np.abs(out[0][1]).max()))
-    for a, b in zip(out[0], out[2]):
-        assert np.array_equal(a, b)
+    for other in out[2::2]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
 
 
 def _loss(T, fl, Ts, fs):

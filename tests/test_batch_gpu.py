@@ -1,6 +1,7 @@
 """GPU tests of batched cavities (dmrt_batch_*): every cavity of a batch must
-equal, bit for bit, a single lattice created with the same inputs, whatever
-the launch shape, graph replay or tuning; small members are checked against
+equal, bit for bit, a single lattice created with the same inputs (one step
+per launch), whatever the launch shape (one or two steps per launch), graph
+replay or tuning; small members are checked against
 the FP64 oracle with the contract tolerances; the full 512-cavity workload
 (10000 steps, in the launch configuration the benchmark times) is checked
 on sampled cavities against single lattices and against stored oracle
@@ -48,13 +49,14 @@ def _fields_equal(a, b, label):
 
 @pytest.fixture(scope="module")
 def small_reference():
-    """Fields of each small-batch cavity from a single lattice, 300 steps."""
+    """Fields of each small-batch cavity from a single lattice, 300 steps of
+    one step per launch."""
     from paper_1503_08406_amd.dmrt import Solver
     cavs, opts = _small_batch()
     out = []
     for i, c in enumerate(cavs):
         _say("single lattice", i, c["nx"], c["ny"])
-        s = Solver(W.batch_member(c, opts))
+        s = Solver(W.batch_member(c, opts), steps_per_launch=1)
         s.step(300)
         out.append(s.fields())
         s.close()
@@ -62,15 +64,23 @@ def small_reference():
 
 
 @pytest.mark.parametrize("rows,blocks,hint", [(4, 0, 0), (8, 0, 0), (4, 8, 0), (8, 1024, 0),
-                                              (4, 0, 1), (4, 0, 2), (8, 0, 3)])
+                                              (4, 0, 1), (4, 0, 2), (8, 0, 3), (0, 0, 0),
+                                              (0, 0, 1), (0, 0, 2), (0, 0, 3)])
 def test_batch_equals_single_lattices(small_reference, rows, blocks, hint):
-    """Any launch shape and any cache policy of the stores (store_hint)."""
+    """Any launch shape (rows 0: two steps per launch, here also with an odd
+    chunk that ends on a one-step launch) and any cache policy of the stores
+    (store_hint)."""
     from paper_1503_08406_amd.dmrt import BatchSolver
     cavs, opts = _small_batch()
     _say("batch", rows, blocks, hint)
     b = BatchSolver(cavs, store_hint=hint, **opts)
     b.set_launch(rows, blocks)
-    b.step(300)
+    if rows == 0:
+        assert b.launch()[0] == 0
+        b.step(151)
+        b.step(149)
+    else:
+        b.step(300)
     assert b.time == 300
     for i in range(len(cavs)):
         _fields_equal(b.fields(i), small_reference[i], "cavity %d" % i)
@@ -92,7 +102,7 @@ def test_batch_graph_and_tune_keep_results(small_reference, tmp_path):
     cache = str(tmp_path / "tune.json")
     rows, blocks, ms = b.tune(trial_steps=3, cache=cache)
     _say("tuned", rows, blocks, ms)
-    assert rows in (4, 8) and blocks % 8 == 0 and ms > 0
+    assert rows in (0, 4, 8) and blocks % 8 == 0 and ms > 0
     assert b.time == 50
     b.step(250)
     for i in range(len(cavs)):
@@ -102,6 +112,32 @@ def test_batch_graph_and_tune_keep_results(small_reference, tmp_path):
     assert b2.launch() == (rows, blocks)
     b.close()
     b2.close()
+
+
+@pytest.mark.parametrize("graph_steps", [6, 16])
+def test_batch_two_steps_per_launch_with_graphs(small_reference, graph_steps):
+    """Graphs of an odd (3) and an even (8) number of two-step launches, then
+    a plain odd remainder: the same bits as single lattices."""
+    from paper_1503_08406_amd.dmrt import BatchSolver
+    cavs, opts = _small_batch()
+    b = BatchSolver(cavs, graph_steps=graph_steps, **opts)
+    b.set_launch(0)
+    b.step(297)
+    b.step(3)
+    assert b.time == 300
+    for i in range(len(cavs)):
+        _fields_equal(b.fields(i), small_reference[i], "cavity %d" % i)
+    b.close()
+
+
+def test_batch_one_step_per_launch_refuses_two_step_shape():
+    from paper_1503_08406_amd.dmrt import BatchSolver, DmrtError
+    cavs, opts = _small_batch()
+    b = BatchSolver(cavs[:2], steps_per_launch=1, **opts)
+    assert b.launch()[0] == 4
+    with pytest.raises(DmrtError):
+        b.set_launch(0)
+    b.close()
 
 
 def test_batch_matches_oracle():
@@ -161,7 +197,7 @@ def test_full_batch_workload():
                      int(np.argmin([c["Ste"] for c in cavs])), 0, 255, 511})
     for i in sample:
         _say("full batch: single lattice", i)
-        s = Solver(W.batch_member(cavs[i], opts), graph_steps=64)
+        s = Solver(W.batch_member(cavs[i], opts), graph_steps=64, steps_per_launch=1)
         s.step(steps)
         _fields_equal(b.fields(i), s.fields(), "cavity %d" % i)
         s.close()

@@ -1,9 +1,10 @@
 """Two time steps per launch (steps_per_launch = 2, the k_step2 kernel)
 against one step per launch: the same per-node arithmetic, so the same bits,
-for every boundary layout, for lattices narrower and wider than one 62-column
-strip, for ragged row counts, with melting, freezing and convection, with
-odd step counts (a last single step) and with graph replay (also graphs of
-an odd number of two-step launches)."""
+for every boundary layout, for lattices narrower and wider than one tile of
+62 columns, for row counts that leave a ragged last tile (and lattices of
+fewer rows than a tile), with melting, freezing and convection, with odd
+step counts (a last single step) and with graph replay (also graphs of an
+odd number of two-step launches)."""
 import sys
 
 import numpy as np
@@ -33,7 +34,7 @@ def _same(a, b, label):
 
 def _pair(case, **over):
     from paper_1503_08406_amd.dmrt import Solver
-    return Solver(case, **over), Solver(case, steps_per_launch=2, **over)
+    return Solver(case, steps_per_launch=1, **over), Solver(case, steps_per_launch=2, **over)
 
 
 def _compare(s1, s2, label):
@@ -65,9 +66,9 @@ def test_two_steps_per_launch_equal_single_steps_on_random_states(oracle_mod, bc
 
 @pytest.mark.parametrize("graph_steps", [0, 6, 8])
 def test_two_steps_per_launch_on_a_melting_cavity(graph_steps):
-    """Convection melting with moving interface (150 x 77, two strips and a
-    ragged third, ragged rows), plain launches and graphs of 3 and 4
-    two-step launches; odd totals."""
+    """Convection melting with moving interface (150 x 77: two tiles and a
+    ragged third across, a ragged last tile row), plain launches and graphs
+    of 3 and 4 two-step launches; odd totals."""
     case = W.cavity(nx=150, ny=77, Ra=3e5, Da=5e-3, Ste=0.5, T_init=0.2)
     s1, s2 = _pair(case, graph_steps=graph_steps)
     for n in (300, 301, 99):
