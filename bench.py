@@ -318,7 +318,7 @@ def flow_point(n=4096, steps=256, warmup=64, graph_steps=64, steps_per_launch=2)
             "nonfinite": int(d["nonfinite"])}
 
 
-def batched(single_mlups, steps=None, trial_steps=16, samples=20, store_hint=0):
+def batched(single_mlups, steps=None, trial_steps=128, samples=20, store_hint=0):
     """The batched workload: 512 cavities of seeded uneven sizes and
     parameters (seed 4), advanced together for 10000 steps with the tuned
     launch shape (one step per launch, or two: rows 0) and graph replay of

@@ -13,6 +13,11 @@ HIPCC_FLAGS = [
     # packed FP32 instructions are disabled: hipcc emits them from plain
     # float code and some of their forms are unreliable on this hardware
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused within one source expression only: whether
+    # two statements fuse would otherwise depend on the surrounding code,
+    # and the one- and two-step kernels (and the batched ones) must round
+    # every node's arithmetic the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

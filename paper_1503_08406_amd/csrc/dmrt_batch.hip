@@ -88,13 +88,8 @@ void k_batch_step(BatchArgs a)
 
 // Two steps of one tile of the list per block: block b works on die b % 8,
 // tile a.die[die] + b / 8 of that die's part.
-#ifndef DMRT_BATCH2_OCC
-#define DMRT_BATCH2_OCC 1
-#endif
-
 template <int SP>
-__global__ __launch_bounds__(TX * T2_WAVES) __attribute__((amdgpu_waves_per_eu(DMRT_BATCH2_OCC)))
-void k_batch_step2(BatchArgs a)
+__global__ __launch_bounds__(TX * T2_WAVES) void k_batch_step2(BatchArgs a)
 {
     __shared__ float tl[TPLANES * T2_WAVES * TX];
     const int xcd = (int)(blockIdx.x & (NXCD - 1));

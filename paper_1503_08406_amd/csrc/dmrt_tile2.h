@@ -16,7 +16,10 @@
 // Both passes run the per-node step of one launch per step (dmrt_node.h: the
 // enthalpy update, the flow part with its wall and solid extrapolation or
 // restart, both collisions) with the same arithmetic, so one launch gives
-// the bits of two single steps.  The intermediate state never leaves the
+// the bits of two single steps.  That holds because multiply-adds are fused
+// within a source expression only (-ffp-contract=on): values that the second
+// pass takes from the first in registers are rounded as the single step's
+// values read back from memory are.  The intermediate state never leaves the
 // chip; all NW rows of a tile load at once, so a block waits for memory
 // twice per launch (the first load batch, then the flow loads) like a block
 // of the single step.  The flow part runs in the node's own lane (no
@@ -45,17 +48,6 @@ __device__ __forceinline__ bool axis_node(int& v, int n, int periodic)
     v %= n;
     if (v < 0) v += n;
     return true;
-}
-
-// A value that the second step takes from the first in a register.  The
-// empty statement hides how it was computed, so the compiler cannot fuse the
-// operation that produced it into the arithmetic of the second step (a
-// multiply and a later add into one fma): the second step sees the rounded
-// value, as a single step that reads it back from memory does.
-__device__ __forceinline__ float opaque(float v)
-{
-    asm volatile("" : "+v"(v));
-    return v;
 }
 
 // Tile slots of the sources x - e_i (i = 0..8) of the pass-B node at `slot`;
@@ -139,11 +131,6 @@ __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const S
             A1->flout.st(o, 0, fl1);
         }
     }
-    n.g[0] = opaque(n.g[0]);
-    fl1 = opaque(fl1);
-    ux = opaque(ux);
-    uy = opaque(uy);
-    f0 = opaque(f0);
     __syncthreads();
 
     // ---- pass B: step k+1 -> k+2 of the tile, from LDS into memory.  A
