@@ -166,25 +166,21 @@ __device__ __forceinline__ void flow_collide_adj(const float (&d)[9], float fl1,
 // Adjoint of the state at step k+1 of node (x, y), gathered from the local
 // adjoints of step k+1 (la: written by the launch for step k+1): the node's
 // own terms plus the adjoints of the pulls its downstream neighbours y + e_i
-// made from it.  flA = f_l^{k+1}, flB = f_l^{k+2}: the flow part exists only
+// made from it.  flA = f_l^{k+1} of the node (already loaded), flB =
+// f_l^{k+2}: the flow part exists only
 // where the node was liquid at k+1, and a node's flow local adjoints only
 // where it was liquid at k+2.  L: d+ (0..8), rho - 1 (9), g+ (10..14),
 // f_l (15), u (16, 17).
-template <bool FLOW>
-__device__ __forceinline__ void gather_state(const Geom& G, const float* __restrict__ la,
-                                             const float* __restrict__ flA,
-                                             const float* __restrict__ flB, int x, int y,
-                                             float (&L)[ADJ_LS])
+// Receivers y + e_i of node (x, y) (rc) and whether each exists (ok).
+__device__ __forceinline__ void gather_receivers(const Geom& G, int x, int y, bool (&ok)[9],
+                                                 size_t (&rc)[9])
 {
-    const size_t pl = (size_t)G.plane;
     const size_t p = (size_t)G.pitch;
     const size_t c = (size_t)y * p + (size_t)x;
     const bool hx = x + 1 < G.nx || G.per_x, lx = x > 0 || G.per_x;
     const bool hy = y + 1 < G.ny || G.per_y, ly = y > 0 || G.per_y;
     const size_t xp = x + 1 < G.nx ? x + 1 : 0, xm = x > 0 ? x - 1 : G.nx - 1;
     const size_t yp = y + 1 < G.ny ? y + 1 : 0, ym = y > 0 ? y - 1 : G.ny - 1;
-    bool ok[9];
-    size_t rc[9];  // receivers y + e_i
     ok[0] = false;
     rc[0] = c;
     ok[1] = hx;
@@ -203,13 +199,36 @@ __device__ __forceinline__ void gather_state(const Geom& G, const float* __restr
     rc[7] = ym * p + xm;
     ok[8] = hx & ly;
     rc[8] = ym * p + xp;
-    float t[10];  // own g terms (0..4), f_l (5), receivers' g pulls (6..9)
+}
+
+// The thermal terms of gather_state, loaded with the node's first batch:
+// own g terms (0..4), own f_l (5), the receivers' g pulls (6..9; loaded from
+// in-lattice addresses even where a receiver is absent).
+__device__ __forceinline__ void gather_thermal_loads(const Geom& G, const float* __restrict__ la,
+                                                     int x, int y, float (&t)[10])
+{
+    const size_t pl = (size_t)G.plane;
+    const size_t c = (size_t)y * (size_t)G.pitch + (size_t)x;
+    bool ok[9];
+    size_t rc[9];
+    gather_receivers(G, x, y, ok, rc);
 #pragma unroll
     for (int i = 0; i < 5; ++i) t[i] = la[(15 + i) * pl + c];
     t[5] = la[29 * pl + c];
 #pragma unroll
-    for (int i = 1; i < 5; ++i) t[5 + i] = la[i * pl + rc[i]];  // in-lattice even when absent
-    pin_loads(t);
+    for (int i = 1; i < 5; ++i) t[5 + i] = la[i * pl + rc[i]];
+}
+
+template <bool FLOW>
+__device__ __forceinline__ void gather_state(const Geom& G, const float* __restrict__ la,
+                                             float flA, const float* __restrict__ flB, int x,
+                                             int y, const float (&t)[10], float (&L)[ADJ_LS])
+{
+    const size_t pl = (size_t)G.plane;
+    const size_t c = (size_t)y * (size_t)G.pitch + (size_t)x;
+    bool ok[9];
+    size_t rc[9];  // receivers y + e_i
+    gather_receivers(G, x, y, ok, rc);
     L[10] = t[0];
 #pragma unroll
     for (int i = 1; i < 5; ++i) L[10 + i] = t[i] + (ok[i] ? t[5 + i] : 0.0f);
@@ -217,7 +236,7 @@ __device__ __forceinline__ void gather_state(const Geom& G, const float* __restr
 #pragma unroll
     for (int i = 0; i < 10; ++i) L[i] = 0.0f;
     L[16] = L[17] = 0.0f;
-    if (FLOW && flA[c] > 0.0f) {
+    if (FLOW && flA > 0.0f) {
         // every load in one batch (stale values of absent terms are loaded
         // from in-lattice addresses and selected away)
         float v[38];  // own d+ (0..8), receivers: f_l (9..16), pulls (17..24), restart (25..32), u (33, 34), own f_l (35)
@@ -290,19 +309,30 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
         if (wn[i]) src[i] = c;
     const bool wall = wxm | wxp | wym | wyp;
 
+    // ---- first load batch: every value whose address is known now (the
+    // flow values follow in a second batch where the node is liquid)
     const float flk = B.fl0[c], fl1 = B.fl1[c];
+    float t[10];  // thermal terms of the state adjoint (gather_state)
+    float Ls[ADJ_LS];
+    if (FIRST) {
+#pragma unroll
+        for (int i = 0; i < ADJ_LS; ++i) Ls[i] = B.ls[i * pl + c];
+    } else {
+        gather_thermal_loads(G, B.la_prev, x, y, t);
+    }
     const float eps = B.eps[c], Ac = B.Ac[c], Bc = B.Bc[c];
-    const bool liqk = FLOW && flk > 0.0f;
-    const bool liq1 = FLOW && fl1 > 0.0f;
-
-    // ---- forward recomputation: pulled g with wall extrapolation
     float q[5], g[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) q[i] = B.g0[i * pl + c];
     g[0] = q[0];
 #pragma unroll
     for (int i = 1; i < 5; ++i) g[i] = B.g0[i * pl + src[i]];
-    const float uxk = liqk ? B.u0[c] : 0.0f, uyk = liqk ? B.u0[pl + c] : 0.0f;
+    const float u0x = FLOW ? B.u0[c] : 0.0f, u0y = FLOW ? B.u0[pl + c] : 0.0f;
+    const bool liqk = FLOW && flk > 0.0f;
+    const bool liq1 = FLOW && fl1 > 0.0f;
+
+    // ---- forward recomputation: pulled g with wall extrapolation
+    const float uxk = liqk ? u0x : 0.0f, uyk = liqk ? u0y : 0.0f;
     float Tk = 0.0f, cu = 0.0f;
     if (wall) {
         Tk = q[0] + ((q[1] + q[3]) + (q[2] + q[4]));
@@ -377,13 +407,15 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
     }
 
     // ---- adjoint of the outputs of this node's step (state k+1)
-    float Ls[ADJ_LS];
-    if (FIRST) {
-#pragma unroll
-        for (int i = 0; i < ADJ_LS; ++i) Ls[i] = B.ls[i * pl + c];
-    } else {
-        gather_state<FLOW>(G, B.la_prev, B.fl1, B.fl2, x, y, Ls);
+    // the gradient accumulators of a node liquid at k+1 (each is added to by
+    // this node only) ride with the flow batch of the gather
+    float ga0 = 0.0f, ga1 = 0.0f, ga2 = 0.0f;
+    if (liq1) {
+        ga0 = B.ga[c];
+        ga1 = B.ga[pl + c];
+        ga2 = B.ga[2 * pl + c];
     }
+    if (!FIRST) gather_state<FLOW>(G, B.la_prev, fl1, B.fl2, x, y, t, Ls);
 
     // ---- reverse: thermal collision (uniform zeta)
     float Lg[5];
@@ -511,7 +543,9 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
     }
     if (!liqk) Luxk = Luyk = 0.0f;
 
-    // ---- outputs
+    // ---- outputs (a node solid at k+1 reads its porosity accumulator here)
+    const bool acc_eps = Leps != 0.0f;
+    if (acc_eps && !liq1) ga0 = B.ga[c];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         B.la[i * pl + c] = Lgp[i];
@@ -527,15 +561,15 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
             B.la[(20 + i) * pl + c] = Lown_d[i];
         }
         B.la[14 * pl + c] = Lrb;
-        B.ga[pl + c] += LAc;
-        B.ga[2 * pl + c] += LBc;
+        B.ga[pl + c] = ga1 + LAc;
+        B.ga[2 * pl + c] = ga2 + LBc;
     }
     if (liqk) {  // u^k also enters the wall extrapolation of g
         B.la[30 * pl + c] = Luxk;
         B.la[31 * pl + c] = Luyk;
     }
     B.la[29 * pl + c] = Lflk;
-    if (Leps != 0.0f) B.ga[c] += Leps;
+    if (acc_eps) B.ga[c] = ga0 + Leps;
 }
 
 // Terminal adjoint of a loss of the final fields: T = sum of g+, so every
