@@ -253,7 +253,7 @@ def hbm_point(n=4096, steps=1000, warmup=100, graph_steps=64, steps_per_launch=2
             traffic = {"bytes": tr["bytes_per_launch"], "fluid_fraction": tr["fluid_fraction"],
                        "GBps": round(tr["bytes_per_launch"] / (launch_ms * 1e-3) / 1e9, 1)}
     return {"workload": "the same cavity at %dx%d (%.2f GB of state), steps %d..%d"
-                        % (n, n, cells * 148 / 1e9, warmup, warmup + steps),
+                        % (n, n, cells * 156 / 1e9, warmup, warmup + steps),
             "value": round(cells * steps / wall / 1e6, 2), "unit": "MLUPS",
             "kernel_ms_per_step": round(kern_ms, 6), "steps_per_launch": spl,
             "roofline": {"bound": "hbm", "achieved": round(bpl / (launch_ms * 1e-3) / 1e9, 1),
@@ -318,7 +318,7 @@ def flow_point(n=4096, steps=256, warmup=64, graph_steps=64, steps_per_launch=2)
             "nonfinite": int(d["nonfinite"])}
 
 
-def batched(single_mlups, steps=None, trial_steps=128, samples=20, store_hint=0):
+def batched(single_mlups, steps=None, trial_steps=128, samples=20, store_hint=0, graph_steps=64):
     """The batched workload: 512 cavities of seeded uneven sizes and
     parameters (seed 4), advanced together for 10000 steps with the tuned
     launch shape (one step per launch, or two: rows 0) and graph replay of
@@ -329,7 +329,7 @@ def batched(single_mlups, steps=None, trial_steps=128, samples=20, store_hint=0)
     from paper_1503_08406_amd.dmrt import BatchSolver
     cavs, opts, nsteps = W.cavity_batch()
     steps = steps or nsteps
-    b = BatchSolver(cavs, graph_steps=64, store_hint=store_hint, **opts)
+    b = BatchSolver(cavs, graph_steps=graph_steps, store_hint=store_hint, **opts)
     rows, blocks, tune_ms = b.tune(trial_steps=trial_steps)
     spl = 2 if rows == 0 else 1
     cells = b.cells
@@ -347,7 +347,7 @@ def batched(single_mlups, steps=None, trial_steps=128, samples=20, store_hint=0)
     assert (bad == 0).all(), "non-finite state in the batch"
     b.close()
     # phase accounting replay
-    r = BatchSolver(cavs, graph_steps=64, store_hint=store_hint, **opts)
+    r = BatchSolver(cavs, graph_steps=graph_steps, store_hint=store_hint, **opts)
     r.set_launch(rows, blocks)
     pts = [(0, int(r.check()[0].sum()))]
     for k in range(1, samples + 1):
@@ -367,7 +367,7 @@ def batched(single_mlups, steps=None, trial_steps=128, samples=20, store_hint=0)
             "value": round(mlups, 2), "unit": "MLUPS",
             "ms_per_step": round(wall * 1e3 / steps, 6),
             "ratio_to_single": round(mlups / single_mlups, 4),
-            "launch": {"rows": rows, "blocks": blocks, "graph_steps": 64,
+            "launch": {"rows": rows, "blocks": blocks, "graph_steps": graph_steps,
                        "steps_per_launch": spl,
                        "tuner_trial_ms_per_step": round(tune_ms, 6)},
             "roofline": {"bound": "hbm", "achieved": round(bpl / (launch_ms * 1e-3) / 1e9, 1),
@@ -552,6 +552,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-cavity measurement")
     ap.add_argument("--batch-steps", type=int, default=0, help="batched steps (0: the workload's)")
+    ap.add_argument("--batch-graph-steps", type=int, default=64,
+                    help="graph replay length of the batch (0: plain launches, for counter runs)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--adjoint-steps", type=int, default=0,
                     help="steps of the adjoint run (0: the workload's 2000; fewer for profiling)")
@@ -690,7 +692,8 @@ def main():
         out["hbm_point"] = hbm_point(steps_per_launch=args.steps_per_launch)
         out["flow_point"] = flow_point(steps_per_launch=args.steps_per_launch)
     if not args.no_batch:
-        out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint)
+        out["batched"] = batched(mlups, steps=args.batch_steps or None, store_hint=args.store_hint,
+                                 graph_steps=args.batch_graph_steps)
         if "hbm_point" in out:
             out["batched"]["ratio_to_single_4096"] = round(
                 out["batched"]["value"] / out["hbm_point"]["value"], 4)

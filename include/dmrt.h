@@ -272,7 +272,8 @@ void dmrt_destroy(dmrt_t *h);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent cavities of uneven size and parameters advance
- * together, one launch per time step over all of them.  Each cavity runs
+ * together, one or two time steps per launch over all of them (see
+ * dmrt_batch_set_launch).  Each cavity runs
  * exactly the step of a single lattice created by dmrt_create with the same
  * grid, boundary, dimensionless numbers and options and with uniform porous
  * fields (eps everywhere, K = Da H^2, F_eps from the Ergun relation of

@@ -1294,11 +1294,13 @@ const char* dmrt_last_error(void) { return g_err.c_str(); }
 // Batches of independent cavities.
 //
 // Every cavity keeps its own planes, laid out as for a single lattice (row
-// pitch a multiple of 64), inside one arena per array kind: f (9 planes),
-// g (5), f_l (1), each double-buffered, and u (2 planes).  A device table of
+// pitch a multiple of 64), inside one arena per array kind: f (10 planes:
+// the populations and rho - 1), g (5), f_l (1) and u (2), each
+// double-buffered.  A device table of
 // Cavity headers gives each cavity's geometry, constants, uniform porous
 // values and plane offsets; a device tile list names (cavity, x0, y0) for
-// every 64 x rows tile.  One launch per time step covers the whole list.
+// every 64 x rows tile, and a second one every 62 x 6 tile of the two-step
+// kernel.  One launch covers the whole list: one time step, or two.
 // ---------------------------------------------------------------------------
 
 struct dmrt_batch {

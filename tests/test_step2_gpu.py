@@ -111,3 +111,17 @@ def test_two_steps_per_launch_full_size_cavity_window():
     s1.step(2000)
     s2.step(2000)
     _same(s1.fields(), s2.fields(), "cavity 1024")
+
+
+def test_launch_steps_reports_where_two_steps_apply():
+    """Two steps per launch by default; one where the option, a literal
+    variant of the thermal model, R2 or another launch shape rules it out
+    (dmrt_launch_steps)."""
+    from paper_1503_08406_amd.dmrt import Solver
+    case = W.cavity(nx=70, ny=37)
+    for over, want in (({}, 2), (dict(steps_per_launch=1), 1), (dict(sigma_mode=1), 1),
+                       (dict(latent_mode=1), 1), (dict(block_rows=8), 1),
+                       (dict(cells_per_lane=2), 1)):
+        s = Solver(case, **over)
+        assert s.launch_steps == want, over
+        s.close()
