@@ -127,14 +127,26 @@ def small_configs():
     return out
 
 
-def window_accounting(case, buf, steps, samples, **over):
-    """Untimed replay of a timed window from its starting checkpoint `buf`:
-    the integral over the window of the number of cells where the flow is
-    solved (trapezoid over at most `samples` points) and the count at its
-    end."""
+def lead_steps(gsteps, spl):
+    """Untimed steps run right before a timed window (from a checkpoint taken
+    that many steps earlier): one graph's worth, or two when a graph holds an
+    odd number of launches, so that the window replays graphs captured for
+    both buffer parities and starts on a device that is already busy (a few
+    launches' worth without graphs)."""
+    if not gsteps:
+        return 4 * spl
+    return gsteps * (2 if (gsteps // spl) % 2 else 1)
+
+
+def window_accounting(case, buf, steps, samples, lead=0, **over):
+    """Untimed replay of a timed window from the checkpoint `buf`, `lead`
+    steps before the window: the integral over the window of the number of
+    cells where the flow is solved (trapezoid over at most `samples` points)
+    and the count at its end."""
     from paper_1503_08406_amd.dmrt import Solver
     s = Solver(case, **over)
     s.load(buf)
+    s.step(lead)
     t0 = s.time
     samples = max(1, min(samples, steps))
     pts = [(0, s.diag()["active"])]
@@ -147,23 +159,20 @@ def window_accounting(case, buf, steps, samples, **over):
     return tot, pts[-1][1]
 
 
-def repeats(case, buf, steps, n=5, **over):
-    """The timed window (`steps` steps from the checkpoint `buf`) timed n
-    more times, each on a fresh solver loaded from the checkpoint (HIP events
-    on its stream): kernel times per step and their median.  Each solver
-    first runs one untimed graph's worth of steps from the checkpoint and is
-    loaded again, so that graph capture stays out of the timed region."""
+def repeats(case, buf, steps, lead, n=5, **over):
+    """The timed window (`steps` steps, `lead` steps after the checkpoint
+    `buf`) timed n more times, each on a fresh solver loaded from the
+    checkpoint (HIP events on its stream): kernel times per step and their
+    median.  Each solver runs the `lead` steps untimed right before the
+    window, as the main run does, so that graph capture stays out of the
+    timed region."""
     import torch
     from paper_1503_08406_amd.dmrt import Solver
-    gs = over.get("graph_steps", 0)
     ms = []
     for _ in range(n):
         s = Solver(case, **over)
         s.load(buf)
-        if gs and steps >= gs:
-            s.step(gs)
-            s.load(buf)
-        s.sync()
+        s.step(lead)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(s.stream)
         s.step(steps)
@@ -279,9 +288,12 @@ def flow_point(n=4096, steps=256, warmup=64, graph_steps=64, steps_per_launch=2)
     over = dict(graph_steps=graph_steps, steps_per_launch=steps_per_launch)
     s = Solver(case, **over)
     spl = s.launch_steps
-    s.step(warmup)
+    lead = min(lead_steps(graph_steps, spl), warmup)
+    s.step(warmup - lead)
     s.sync()
-    buf = s.save()
+    buf = s.save()  # lead steps before the window
+    s.step(lead)
+    s.sync()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(s.stream)
@@ -292,9 +304,9 @@ def flow_point(n=4096, steps=256, warmup=64, graph_steps=64, steps_per_launch=2)
     kern_ms = ev0.elapsed_time(ev1) / steps
     d = s.diag()
     s.close()
-    act, act_end = window_accounting(case, buf, steps, 16, **over)
-    rep = repeats(case, buf, steps, n=3, **over)
-    one = repeats(case, buf, steps, n=3, graph_steps=graph_steps, steps_per_launch=1)
+    act, act_end = window_accounting(case, buf, steps, 16, lead, **over)
+    rep = repeats(case, buf, steps, lead, n=3, **over)
+    one = repeats(case, buf, steps, lead, n=3, graph_steps=graph_steps, steps_per_launch=1)
     del buf
     cells = n * n
     ff = act / (cells * steps)
@@ -596,26 +608,27 @@ def main():
         print("copy probe: 3 x 1 GiB device-to-device copies", flush=True)
         del a, b
 
-    # untimed: advance to the start of the window, then the warm-up steps; the
-    # last graph's worth of them starts at the window's buffer parity, so the
-    # window replays a graph captured here
+    # untimed: advance to the start of the window, then the warm-up steps.
+    # The checkpoint for the replays below is taken `lead` steps before the
+    # window; those last steps run right before it (in the replays as well),
+    # so that the window replays graphs captured for both buffer parities and
+    # starts on a busy device.
     s = Solver(case, **over)
     spl = s.launch_steps
     pre = args.start + args.warmup
-    last = gsteps if gsteps and pre >= gsteps else 0
-    s.step(pre - last)
-    s.step(last)
+    lead = min(lead_steps(gsteps, spl), pre)
+    s.step(pre - lead)
     s.sync()
-    buf = s.save()  # the window's starting state (for the replays below)
-    t_start = s.time
-    torch.cuda.synchronize()
+    buf = s.save()
+    s.step(lead)
+    t_start = pre
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)  # after the warm-up steps, outside the wall-clock bracket
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(s.stream)
     s.step(args.steps)
     ev1.record(s.stream)
-    s.sync()
-    torch.cuda.synchronize()
+    torch.cuda.synchronize()  # the whole device, the solver's stream included
     t1 = time.perf_counter()
     wall = t1 - t0
     kern_ms = ev0.elapsed_time(ev1) / args.steps
@@ -625,13 +638,13 @@ def main():
     cells = case["nx"] * case["ny"]
     mlups = cells * args.steps / wall / 1e6
 
-    act_steps, act_end = window_accounting(case, buf, args.steps, 50, **over)
+    act_steps, act_end = window_accounting(case, buf, args.steps, 50, lead, **over)
     fluid_frac = act_steps / (cells * args.steps)
     bytes_per_launch = (BYTES_FLUID * fluid_frac + BYTES_SOLID * (1 - fluid_frac)) * cells
-    rep = repeats(case, buf, args.steps, **over)
+    rep = repeats(case, buf, args.steps, lead, **over)
     one = None
     if spl == 2:
-        one = repeats(case, buf, args.steps, n=3, **dict(over, steps_per_launch=1))
+        one = repeats(case, buf, args.steps, lead, n=3, **dict(over, steps_per_launch=1))
     del buf
     med_ms = rep["median_kernel_ms"]  # per step
     launch_ms = med_ms * spl
