@@ -33,7 +33,12 @@ namespace dmrtk {
 namespace {
 
 constexpr int T2_W = 62;    // tile width (pass-B columns)
-constexpr int T2_WAVES = 8; // waves of a block: tile rows + 2 (measured best of 6 to 16)
+// Waves of a block: tile rows + 2 (a build-time knob; 8 measured best of
+// 6 to 16).
+#ifndef DMRT_T2_WAVES
+#define DMRT_T2_WAVES 8
+#endif
+constexpr int T2_WAVES = DMRT_T2_WAVES;
 constexpr int T2_ROWS = T2_WAVES - 2;
 // LDS planes of a tile: f+_i at TF + i - 1 (i = 1..8), rho - 1, g+_i at
 // TG + i - 1 (i = 1..4), f_l^{k+1}.
