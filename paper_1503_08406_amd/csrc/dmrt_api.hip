@@ -127,6 +127,26 @@ struct dmrt {
     dmrtk::R2Bufs R{};
 };
 
+// Tiling constants for tiles of w x h nodes (see dmrt_internal.h).
+namespace dmrtk {
+void set_tiling(Geom& G, int w, int h)
+{
+    G.st_tx = (G.nx + w - 1) / w;
+    G.st_ntiles = G.st_tx * ((G.ny + h - 1) / h);
+    G.st_per_xcd = (G.st_ntiles + NXCD - 1) / NXCD;
+    const uint32_t d = (uint32_t)G.st_tx;
+    if (d == 1) {
+        G.st_magic = 0;
+        G.st_shift = 0;
+    } else {
+        int l = 0;
+        while ((1ull << l) < d) ++l;
+        G.st_magic = (uint32_t)(((((uint64_t)1 << l) - d) << 32) / d + 1);
+        G.st_shift = l;
+    }
+}
+}  // namespace dmrtk
+
 namespace {
 
 int derive_impl(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
@@ -297,20 +317,7 @@ void fill_geom(Geom& G, int nx, int ny, const dmrt_bc& bc, const dmrt_opts& o)
 // 32-bit "add" form: l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1).
 void set_step_tiling(Geom& G)
 {
-    const int rows = G.block_rows * G.cells_per_lane;
-    G.st_tx = (G.nx + dmrtk::TX - 1) / dmrtk::TX;
-    G.st_ntiles = G.st_tx * ((G.ny + rows - 1) / rows);
-    G.st_per_xcd = (G.st_ntiles + dmrtk::NXCD - 1) / dmrtk::NXCD;
-    const uint32_t d = (uint32_t)G.st_tx;
-    if (d == 1) {
-        G.st_magic = 0;
-        G.st_shift = 0;
-    } else {
-        int l = 0;
-        while ((1ull << l) < d) ++l;
-        G.st_magic = (uint32_t)(((((uint64_t)1 << l) - d) << 32) / d + 1);
-        G.st_shift = l;
-    }
+    dmrtk::set_tiling(G, dmrtk::TX, G.block_rows * G.cells_per_lane);
 }
 
 int copy_in(void* dst, const void* src, size_t bytes, hipStream_t s)
@@ -1461,6 +1468,11 @@ dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p, bool two = false)
     a.uin = b->u[p];
     a.uout = b->u[1 - p];
     a.store = b->store;
+    // parity p's f, g, f_l and u arenas lie in one half of the allocation
+    const uint64_t half = (uint64_t)((const char*)b->f[1] - (const char*)b->f[0]);
+    a.win = (const char*)b->f[p];
+    a.wout = (const char*)b->f[1 - p];
+    a.win_bytes = half < (1ull << 32) ? (uint32_t)half : 0u;
     return a;
 }
 

@@ -49,12 +49,13 @@ __device__ __forceinline__ bool tile_origin(const Geom& G, int& x0, int& y0)
     return true;
 }
 
-// Tile origin of the step kernel from the host-computed tiling constants:
+// Tile origin of the step kernel from the host-computed tiling constants
+// (tiles W wide):
 // q = tile / st_tx via q = (hi + ((t - hi) >> 1)) >> (shift - 1), hi =
 // mulhi(t, magic) (division by an invariant integer, Granlund & Montgomery).
 // Branch-free, so that nothing stands between the kernel-argument loads and
 // the first memory batch.
-template <int ROWS>
+template <int ROWS, int W = TX>
 __device__ __forceinline__ bool step_tile_origin(const Geom& G, int& x0, int& y0)
 {
     const uint32_t b = blockIdx.x;
@@ -62,7 +63,7 @@ __device__ __forceinline__ bool step_tile_origin(const Geom& G, int& x0, int& y0
     const uint32_t hi = __umulhi(tile, G.st_magic);
     const uint32_t qd = (hi + ((tile - hi) >> 1)) >> ((uint32_t)(G.st_shift - 1) & 31u);
     const uint32_t q = G.st_shift == 0 ? tile : qd;  // shift 0: one tile per row
-    x0 = (int)(tile - q * (uint32_t)G.st_tx) * TX;
+    x0 = (int)(tile - q * (uint32_t)G.st_tx) * W;
     y0 = (int)q * ROWS;
     return tile < (uint32_t)G.st_ntiles;
 }
@@ -121,6 +122,37 @@ struct BufIOT {
     }
 };
 using BufIO = BufIOT<ST_PLAIN>;
+
+// WinIOT: the arrays of a step inside one window of fewer than 4 GB
+// (StepBufs::win), all through one buffer resource over the window; an
+// array is its byte offset in the window, added to the plane offset in the
+// instruction's scalar offset.  One resource for all arrays instead of one
+// each (four scalar registers apiece) leaves the step kernels' scalar
+// values in registers rather than spilled to vector-register lanes.  PAIR:
+// two windows, the arrays written in StepBufs::wout.
+template <int SP, bool PAIR = false>
+struct WinIOT {
+    using off_t = uint32_t;
+    static constexpr bool in_window = true;
+    static constexpr bool pair = PAIR;
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t a;  // byte offset of the array in the window
+    __device__ __forceinline__ WinIOT(const char* win, uint32_t nbytes, const float* p)
+        : r(__builtin_amdgcn_make_buffer_rsrc((void*)win, (short)0, (int)nbytes, 0x00020000)),
+          a((uint32_t)((const char*)p - win))
+    {
+    }
+    __device__ __forceinline__ float ld(off_t o, off_t plane_off) const
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                             r, o, __builtin_amdgcn_readfirstlane(a + plane_off), 0));
+    }
+    __device__ __forceinline__ void st(off_t o, off_t plane_off, float v) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o,
+                                              __builtin_amdgcn_readfirstlane(a + plane_off), SP);
+    }
+};
 
 template <int SP>
 struct PtrIOT {

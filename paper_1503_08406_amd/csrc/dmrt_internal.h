@@ -80,7 +80,19 @@ struct StepBufs {
     int* __restrict__ it_max;
     const float* __restrict__ r2f; // R2: f_l^{k+1} from the global iteration
     int r2_its;                    // R2: its sweeps
+    // A window of device memory of fewer than 4 GB that holds every array
+    // above, for kernels that address them all through one buffer resource
+    // (null where they do not fit one); with a window pair, win holds the
+    // arrays read (state k, the porous planes) and wout those written.
+    const char* win = nullptr;
+    const char* wout = nullptr;
+    uint32_t win_bytes = 0, wout_bytes = 0;
 };
+
+// Sets G's tiling constants (st_*) for tiles of w x h nodes: tiles per row,
+// in total and per die, and the magic number dividing a tile index by the
+// tiles per row.
+void set_tiling(Geom& G, int w, int h);
 
 hipError_t launch_step(const Geom& G, const Phys& P, const StepBufs& B, bool flow,
                        bool counted, hipStream_t s);
@@ -134,6 +146,12 @@ struct BatchArgs {
     const float* uin;  // u^k (two planes per cavity at its u_off)
     float* uout;       // u^{k+1}, or u^{k+2} after two steps
     int store;  // cache policy of the state stores (ST_*)
+    // the halves of the state arena that hold the arrays read and written
+    // (f, g, f_l, u of one parity each), when a half is under 4 GB; else
+    // win_bytes is 0
+    const char* win;
+    const char* wout;
+    uint32_t win_bytes;
 };
 
 // Persistent batched step: `blocks` blocks (a multiple of 8) of 64 x rows

@@ -7,6 +7,30 @@
 
 namespace dmrtk {
 
+// An access object of kind IO for the array of nbytes at p (WinIOT: inside
+// the window of B).
+template <class IO, class = void>
+struct InWindow {
+    static constexpr bool value = false;
+};
+template <class IO>
+struct InWindow<IO, decltype((void)IO::in_window)> {
+    static constexpr bool value = true;
+};
+
+template <class IO, bool OUT>
+__device__ __forceinline__ IO array_io(const StepBufs& B, const float* p, uint64_t nbytes)
+{
+    if constexpr (InWindow<IO>::value) {
+        if constexpr (OUT && IO::pair)
+            return IO(B.wout, B.wout_bytes, p);
+        else
+            return IO(B.win, B.win_bytes, p);
+    } else {
+        return IO(p, nbytes);
+    }
+}
+
 // The state arrays of one launch.
 template <class IO>
 struct Arrays {
@@ -17,12 +41,14 @@ struct Arrays {
     float eps_u = 0.0f, Ac_u = 0.0f, Bc_u = 0.0f;
     __device__ __forceinline__ Arrays(const Geom& G, const StepBufs& B)
         : pb((typename IO::off_t)G.plane * 4u),
-          fin(B.fin, FQ * (uint64_t)pb), fout(B.fout, FQ * (uint64_t)pb),
-          gin(B.gin, 5 * (uint64_t)pb), gout(B.gout, 5 * (uint64_t)pb),
-          flin(B.flin, pb), flout(B.flout, pb),
-          uv(B.ux, 2 * (uint64_t)pb),    // ux plane, then uy plane (u^{k+1})
-          uvin(B.uin ? B.uin : B.ux, 2 * (uint64_t)pb),  // u^k
-          stat(B.eps, 3 * (uint64_t)pb)  // eps, Ac, Bc planes
+          fin(array_io<IO, false>(B, B.fin, FQ * (uint64_t)pb)),
+          fout(array_io<IO, true>(B, B.fout, FQ * (uint64_t)pb)),
+          gin(array_io<IO, false>(B, B.gin, 5 * (uint64_t)pb)),
+          gout(array_io<IO, true>(B, B.gout, 5 * (uint64_t)pb)),
+          flin(array_io<IO, false>(B, B.flin, pb)), flout(array_io<IO, true>(B, B.flout, pb)),
+          uv(array_io<IO, true>(B, B.ux, 2 * (uint64_t)pb)),  // ux plane, then uy plane (u^{k+1})
+          uvin(array_io<IO, false>(B, B.uin ? B.uin : B.ux, 2 * (uint64_t)pb)),  // u^k
+          stat(array_io<IO, false>(B, B.eps, 3 * (uint64_t)pb))  // eps, Ac, Bc planes
     {
     }
 };

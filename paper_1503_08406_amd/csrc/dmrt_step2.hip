@@ -8,21 +8,24 @@ namespace {
 
 // Tiles numbered row-major; blocks are handed to the dies round-robin and
 // die d takes a contiguous run of tiles, so neighbouring tiles (which share
-// their ring of nodes and the rows they pull from) run on the same die.
+// their ring of nodes and the rows they pull from) run on the same die.  The
+// tile of a block comes from host-computed constants (no division on the
+// device).
 // MID: the state k+1 is stored too, into the arrays of B1 (recorded runs).
+// With one buffer resource for all arrays (WinIOT) the kernel is compiled
+// for 7 waves per SIMD, which fits its scalar registers into 94 with the
+// same few spills as without the bound: measured 3-7 % faster than the
+// unbounded build (106 scalar registers), the liquid-started lattice
+// unchanged; a bound of 8 spills 33 and is slower where flow dominates.
 template <class IO, bool FLOW, int NW, bool MID>
-__global__ __launch_bounds__(TX * NW) void k_step2(Geom G, Phys P, StepBufs B, StepBufs B1)
+__global__ __launch_bounds__(TX * NW) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? 7 : 1)))
+void k_step2(Geom G, Phys P, StepBufs B, StepBufs B1)
 {
-    constexpr int RB = NW - 2;
     __shared__ float tl[TPLANES * NW * TX];
-    const int nsx = (G.nx + T2_W - 1) / T2_W;
-    const int ntiles = nsx * ((G.ny + RB - 1) / RB);
-    const int per = (ntiles + NXCD - 1) / NXCD;
-    const int b = (int)blockIdx.x;
-    const int tile = (b % NXCD) * per + b / NXCD;
-    if (tile >= ntiles) return;  // the whole block: no barrier is left waiting
+    int x0, y0;
+    // G's tiling constants are those of the tiles of this kernel
+    if (!step_tile_origin<NW - 2, T2_W>(G, x0, y0)) return;  // the whole block
     const Arrays<IO> A(G, B);
-    const int x0 = (tile % nsx) * T2_W, y0 = (tile / nsx) * RB;
     if (MID) {
         const Arrays<IO> A1(G, B1);
         tile_step2<IO, FLOW, NW, false, true>(G, P, B, A, x0, y0, tl, &A1);
@@ -36,13 +39,13 @@ hipError_t launch_io2(const Geom& G, const Phys& P, const StepBufs& B, const Ste
                       hipStream_t s)
 {
     constexpr int NW = T2_WAVES;
-    const int nsx = (G.nx + T2_W - 1) / T2_W;
-    const int ntiles = nsx * ((G.ny + NW - 3) / (NW - 2));
-    const dim3 grd(NXCD * ((ntiles + NXCD - 1) / NXCD));
+    Geom Gt = G;
+    set_tiling(Gt, T2_W, NW - 2);
+    const dim3 grd(NXCD * Gt.st_per_xcd);
     if (mid)
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true>), grd, dim3(TX, NW), 0, s, G, P, B, *mid);
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);
     else
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false>), grd, dim3(TX, NW), 0, s, G, P, B, B);
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
     return hipGetLastError();
 }
 
@@ -53,16 +56,70 @@ bool step2_supported(const Geom& G, const Phys& P)
     return !G.wide && G.block_rows == 4 && G.cells_per_lane == 1 && !P.sig_mode && !P.ke_mode;
 }
 
+namespace {
+
+// Sets the window of B (and of mid, the same one) when every array of the
+// launch lies within 4 GB of the lowest; false otherwise.
+bool set_window(const Geom& G, StepBufs& B, StepBufs* mid)
+{
+    const uint64_t pb = (uint64_t)G.plane * 4u;
+    struct Span {
+        const void* p;
+        uint64_t n;
+    };
+    const Span in[] = {{B.fin, FQ * pb},  {B.fout, FQ * pb}, {B.gin, 5 * pb},
+                       {B.gout, 5 * pb},  {B.flin, pb},      {B.flout, pb},
+                       {B.ux, 2 * pb},    {B.uin ? B.uin : B.ux, 2 * pb}, {B.eps, 3 * pb}};
+    uint64_t lo = ~0ull, hi = 0;
+    auto add = [&](const void* p, uint64_t n) {
+        const uint64_t a = (uint64_t)(uintptr_t)p;
+        lo = a < lo ? a : lo;
+        hi = a + n > hi ? a + n : hi;
+    };
+    for (const Span& sp : in) add(sp.p, sp.n);
+    if (mid) {
+        add(mid->fout, FQ * pb);
+        add(mid->gout, 5 * pb);
+        add(mid->flout, pb);
+        add(mid->ux, 2 * pb);
+    }
+    if (hi - lo >= (1ull << 32)) return false;
+    B.win = (const char*)(uintptr_t)lo;
+    B.win_bytes = (uint32_t)(hi - lo);
+    if (mid) {
+        mid->win = B.win;
+        mid->win_bytes = B.win_bytes;
+    }
+    return true;
+}
+
+template <int SP>
+using WinIO1 = WinIOT<SP, false>;
+
+template <template <int> class IOT>
+hipError_t launch_policy(const Geom& G, const Phys& P, const StepBufs& B, bool flow,
+                         hipStream_t s, const StepBufs* mid)
+{
+    if (G.store == ST_WT)
+        return flow ? launch_io2<IOT<ST_WT>, true>(G, P, B, mid, s)
+                    : launch_io2<IOT<ST_WT>, false>(G, P, B, mid, s);
+    if (G.store == ST_NT)
+        return flow ? launch_io2<IOT<ST_NT>, true>(G, P, B, mid, s)
+                    : launch_io2<IOT<ST_NT>, false>(G, P, B, mid, s);
+    return flow ? launch_io2<IOT<ST_PLAIN>, true>(G, P, B, mid, s)
+                : launch_io2<IOT<ST_PLAIN>, false>(G, P, B, mid, s);
+}
+
+}  // namespace
+
 hipError_t launch_step2(const Geom& G, const Phys& P, const StepBufs& B, bool flow, hipStream_t s,
                         const StepBufs* mid)
 {
-    if (G.store == ST_WT)
-        return flow ? launch_io2<BufIOT<ST_WT>, true>(G, P, B, mid, s)
-                    : launch_io2<BufIOT<ST_WT>, false>(G, P, B, mid, s);
-    if (G.store == ST_NT)
-        return flow ? launch_io2<BufIOT<ST_NT>, true>(G, P, B, mid, s)
-                    : launch_io2<BufIOT<ST_NT>, false>(G, P, B, mid, s);
-    return flow ? launch_io2<BufIO, true>(G, P, B, mid, s) : launch_io2<BufIO, false>(G, P, B, mid, s);
+    StepBufs Bw = B, Mw;
+    if (mid) Mw = *mid;
+    if (set_window(G, Bw, mid ? &Mw : nullptr))
+        return launch_policy<WinIO1>(G, P, Bw, flow, s, mid ? &Mw : nullptr);
+    return launch_policy<BufIOT>(G, P, B, flow, s, mid);
 }
 
 }  // namespace dmrtk
