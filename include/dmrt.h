@@ -129,6 +129,12 @@ typedef struct {
                            the intermediate state stays in LDS, so a node update
                            moves half the bytes.  The results are the same bits;
                            default 2                                              */
+    int32_t addressing; /* how the two-step kernels reach the state: 0 through one
+                           buffer resource over the memory window that holds every
+                           array of a launch, where that window is under 4 GB (a
+                           batch: one per half of its state, under 4 GB each), else
+                           one resource per array; 1 always one per array.  The
+                           results are the same bits; default 0                   */
 } dmrt_opts;
 
 /* Lattice constants derived from the dimensionless inputs (Sec. 4.3). */

@@ -213,6 +213,7 @@ int check_opts(const dmrt_opts& o)
         return fail(DMRT_EINVAL, "record_mode must be 0, 1 or 2");
     if (o.steps_per_launch < 0 || o.steps_per_launch > 2)
         return fail(DMRT_EINVAL, "steps_per_launch must be 0, 1 or 2");
+    if (o.addressing < 0 || o.addressing > 1) return fail(DMRT_EINVAL, "addressing must be 0 or 1");
     if (!finite_pos(o.cps_ratio) || !finite_pos(o.cm_ratio) || !finite_pos(o.ks_ratio) ||
         !finite_pos(o.km_ratio))
         return fail(DMRT_EINVAL, "cps_ratio, cm_ratio, ks_ratio, km_ratio must be > 0");
@@ -309,6 +310,7 @@ void fill_geom(Geom& G, int nx, int ny, const dmrt_bc& bc, const dmrt_opts& o)
     G.cells_per_lane = (o.cells_per_lane && !variant) ? o.cells_per_lane : 1;
     // 32-bit buffer addressing while the largest array (9 planes) fits 4 GB
     G.wide = (uint64_t)G.plane * 4 * dmrtk::FQ >= (1ull << 32) ? 1 : 0;
+    G.per_array = o.addressing == 1;
     set_step_tiling(G);
 }
 
@@ -752,6 +754,7 @@ void dmrt_opts_default(dmrt_opts* o)
     o->km_ratio = 1.0;
     o->record_mode = 0;
     o->steps_per_launch = 2;
+    o->addressing = 0;
 }
 
 int dmrt_derive(const dmrt_grid* grid, double Ra, double Da, double Pr, double Ste,
@@ -1332,6 +1335,7 @@ struct dmrt_batch {
     // two steps per launch: allowed (steps_per_launch 2), in effect, and its
     // tile list cut into die parts, launched with one block per tile
     bool two_ok = false, two = false;
+    bool per_array = false;  // one buffer resource per array (addressing 1)
     int4* dtiles2 = nullptr;
     int die2[dmrtk::NXCD + 1]{};
     int blocks2 = 0;
@@ -1472,7 +1476,7 @@ dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p, bool two = false)
     const uint64_t half = (uint64_t)((const char*)b->f[1] - (const char*)b->f[0]);
     a.win = (const char*)b->f[p];
     a.wout = (const char*)b->f[1 - p];
-    a.win_bytes = half < (1ull << 32) ? (uint32_t)half : 0u;
+    a.win_bytes = !b->per_array && half < (1ull << 32) ? (uint32_t)half : 0u;
     return a;
 }
 
@@ -1694,6 +1698,7 @@ int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opt
     if (e != hipSuccess) return bail(fail(DMRT_EDEVICE, "initial state: %s", hipGetErrorString(e)));
     if ((rc = batch_layout(b, o.block_rows ? o.block_rows : 4, 0))) return bail(rc);
     b->two_ok = o.steps_per_launch == 2;
+    b->per_array = o.addressing == 1;
     if (b->two_ok && (rc = batch_layout2(b))) return bail(rc);
     b->two = b->two_ok;
     *out = b;

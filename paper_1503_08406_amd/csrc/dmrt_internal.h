@@ -60,6 +60,7 @@ struct Geom {
     int st_shift;
     int wide;           // 1: 64-bit addressing (arrays beyond a 4 GB window)
     int store;          // cache policy of the default step's stores (ST_*)
+    int per_array;      // 1: the two-step kernel uses one buffer resource per array
 };
 
 // Device buffers of one step (deviation populations for f).

@@ -117,7 +117,7 @@ hipError_t launch_step2(const Geom& G, const Phys& P, const StepBufs& B, bool fl
 {
     StepBufs Bw = B, Mw;
     if (mid) Mw = *mid;
-    if (set_window(G, Bw, mid ? &Mw : nullptr))
+    if (!G.per_array && set_window(G, Bw, mid ? &Mw : nullptr))
         return launch_policy<WinIO1>(G, P, Bw, flow, s, mid ? &Mw : nullptr);
     return launch_policy<BufIOT>(G, P, B, flow, s, mid);
 }

@@ -43,7 +43,7 @@ class Opts(C.Structure):
                ("sigma_mode", C.c_int32), ("ke_mode", C.c_int32), ("latent_mode", C.c_int32),
                ("store_hint", C.c_int32), ("cps_ratio", C.c_double), ("cm_ratio", C.c_double),
                ("ks_ratio", C.c_double), ("km_ratio", C.c_double), ("record_mode", C.c_int32),
-               ("steps_per_launch", C.c_int32)]
+               ("steps_per_launch", C.c_int32), ("addressing", C.c_int32)]
 
 
 class Cavity(C.Structure):

@@ -48,7 +48,7 @@ def _args(**over):
 
 @pytest.mark.parametrize("what", ["grid", "periodic_pair", "kind", "tau", "TlTs", "rate",
                                   "graph_odd", "Ste", "noeps", "varpi", "sigma_mode", "ratio",
-                                  "store_hint", "cps_enthalpy", "r2_sweeps"])
+                                  "store_hint", "cps_enthalpy", "r2_sweeps", "addressing"])
 def test_create_rejects_bad_arguments_without_device(what):
     from paper_1503_08406_amd import dmrt
     lib = dmrt.lib()
@@ -82,6 +82,8 @@ def test_create_rejects_bad_arguments_without_device(what):
         o.store_hint = 4
     elif what == "r2_sweeps":
         o.latent_mode, o.fl_maxit = 1, 5000
+    elif what == "addressing":
+        o.addressing = 2
     elif what == "cps_enthalpy":
         # Eq. (41) needs En_l = T_l + 1/St above En_s = c_ps T_s
         o.sigma_mode, o.cps_ratio, o.T_s, o.T_l = 1, 10.0, 0.5, 0.6

@@ -111,9 +111,10 @@ def test_adjoint_matches_oracle_adjoint(kind):
 def test_record_modes_give_the_same_gradients_and_state():
     """Keeping every state of the run (no recomputation) and keeping sqrt(n)
     checkpoints (segments recomputed), each recorded (and recomputed) with one
-    or two steps per launch, give the same gradients bit for bit; the
-    recorded run ends at the state dmrt_step reaches, and a second recording
-    (graph replay) repeats the first."""
+    or two steps per launch (these with either addressing of the two-step
+    kernel), give the same gradients bit for bit; the recorded run ends at
+    the state dmrt_step reaches, and a second recording (graph replay)
+    repeats the first."""
     from paper_1503_08406_amd.dmrt import Solver
     case, steps, wT, wf = _case("liquid")
     steps += 3  # not a square, odd
@@ -121,15 +122,15 @@ def test_record_modes_give_the_same_gradients_and_state():
     ref.step(steps)
     Fr = ref.fields()
     out = []
-    for mode, spl in ((2, 2), (1, 2), (2, 1), (1, 1)):
-        s = Solver(case, fl_tol=1e-7, record_mode=mode, steps_per_launch=spl)
+    for mode, spl, addr in ((2, 2, 0), (1, 2, 0), (2, 1, 0), (1, 1, 0), (2, 2, 1), (1, 2, 1)):
+        s = Solver(case, fl_tol=1e-7, record_mode=mode, steps_per_launch=spl, addressing=addr)
         assert s.launch_steps == spl
         for rep in range(2):
             s.reset()
             s.record(steps)
             F = s.fields()
             for k in F:
-                assert np.array_equal(F[k], Fr[k]), (mode, spl, rep, k)
+                assert np.array_equal(F[k], Fr[k]), (mode, spl, addr, rep, k)
             assert s.time == steps * (rep + 1)
             g = s.adjoint(wT, wf)
             if rep:

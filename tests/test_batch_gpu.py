@@ -91,6 +91,20 @@ def test_batch_equals_single_lattices(small_reference, rows, blocks, hint):
     b.close()
 
 
+def test_batch_per_array_addressing(small_reference):
+    """Two steps per launch with one buffer resource per array (addressing 1)
+    instead of one per half of the state arena: the same bits."""
+    from paper_1503_08406_amd.dmrt import BatchSolver
+    cavs, opts = _small_batch()
+    b = BatchSolver(cavs, addressing=1, **opts)
+    b.set_launch(0, 0)
+    b.step(151)
+    b.step(149)
+    for i in range(len(cavs)):
+        _fields_equal(b.fields(i), small_reference[i], "cavity %d" % i)
+    b.close()
+
+
 def test_batch_graph_and_tune_keep_results(small_reference, tmp_path):
     """Graph replay (even chunks plus a plain remainder) and the tuner (which
     times candidates on a copy of the state) leave the results unchanged; the

@@ -113,6 +113,32 @@ def test_two_steps_per_launch_full_size_cavity_window():
     _same(s1.fields(), s2.fields(), "cavity 1024")
 
 
+@pytest.mark.parametrize("bc", list(BCS))
+def test_per_array_addressing_gives_the_same_bits(oracle_mod, bc):
+    """The two-step kernel with one buffer resource per array (addressing 1,
+    the form for arrays that do not fit one 4 GB window) against the default
+    single resource over the state's window and against one step per
+    launch, on random mixed states."""
+    from paper_1503_08406_amd.dmrt import Solver
+    nx, ny = 70, 37
+    kinds, tw = BCS[bc]
+    L = oracle_mod.lattice()
+    case = W.make_case("rand", nx, ny, kinds, tw, Ra=2e5, Da=2e-3, Pr=1.0, Ste=0.8, eps=0.45,
+                       H=64, T_init=0.4, T_s=0.38, T_l=0.42, convective=1)
+    f, g, fl = W.random_state(nx, ny, 11, L["w9"], L["w5"])
+    s1, s2 = _pair(case)
+    s3 = Solver(case, steps_per_launch=2, addressing=1)
+    assert s3.launch_steps == 2
+    for s in (s1, s2, s3):
+        s.set_state(f, g, fl)
+    for n in (2, 1, 4, 9):
+        _say("addressing", bc, n)
+        for s in (s1, s2, s3):
+            s.step(n)
+        _compare(s1, s2, "%s window after %d" % (bc, s1.time))
+        _compare(s1, s3, "%s per array after %d" % (bc, s1.time))
+
+
 def test_launch_steps_reports_where_two_steps_apply():
     """Two steps per launch by default; one where the option, a literal
     variant of the thermal model, R2 or another launch shape rules it out
