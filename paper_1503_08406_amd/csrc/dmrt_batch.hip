@@ -86,17 +86,30 @@ void k_batch_step(BatchArgs a)
     }
 }
 
+// Waves of a two-step block in a batch: tiles of 62 x 10 nodes.  Taller
+// than the single lattice's (8 waves, 62 x 6): measured 1.9 % faster on the
+// 512-cavity workload (538.0 against 548.4 us per step) and even on batches
+// of 512^2 cavities; the single lattice's fast cases lose 8 % at 12 waves.
+#ifndef DMRT_B2_WAVES
+#define DMRT_B2_WAVES 12
+#endif
+#ifndef DMRT_B2_OCC
+#define DMRT_B2_OCC 6
+#endif
+constexpr int B2_WAVES = DMRT_B2_WAVES;
+
 // Two steps of one tile of the list per block: block b works on die b % 8,
 // tile a.die[die] + b / 8 of that die's part.  IO: BufIOT, or WinIOT with
-// the window pair of the two halves of the state arena, compiled for 7
-// waves per SIMD as the single-lattice kernel: 94 scalar registers with 15
-// spilled (106 with 23 spilled for BufIOT), measured 4.6 % faster on the
-// batch of 512 cavities; without the bound 0.8 %, with a bound of 8 slower.
+// the window pair of the two halves of the state arena, compiled for 6
+// waves per SIMD (two 12-wave blocks per CU, as the LDS allows); at 8-wave
+// blocks and 7 waves per SIMD this took 94 scalar registers with 15 spilled
+// (106 with 23 spilled for BufIOT) and measured 4.6 % faster on the batch of
+// 512 cavities; without the bound 0.8 %, with a bound of 8 slower.
 template <class IO>
-__global__ __launch_bounds__(TX * T2_WAVES) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? 7 : 1)))
+__global__ __launch_bounds__(TX * B2_WAVES) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? DMRT_B2_OCC : 1)))
 void k_batch_step2(BatchArgs a)
 {
-    __shared__ float tl[TPLANES * T2_WAVES * TX];
+    __shared__ float tl[TPLANES * B2_WAVES * TX];
     const int xcd = (int)(blockIdx.x & (NXCD - 1));
     const int t = a.die[xcd] + (int)(blockIdx.x >> 3);
     if (t >= a.die[xcd + 1]) return;  // the whole block: no barrier is left waiting
@@ -123,7 +136,7 @@ void k_batch_step2(BatchArgs a)
     A.eps_u = C.eps;
     A.Ac_u = C.Ac;
     A.Bc_u = C.Bc;
-    tile_step2<IO, true, T2_WAVES, true>(C.G, C.P, B, A, tile.y, tile.z, tl);
+    tile_step2<IO, true, B2_WAVES, true>(C.G, C.P, B, A, tile.y, tile.z, tl);
 }
 
 // Per-cavity partial counts (blockIdx.y = cavity): liquid nodes (f_l > 0)
@@ -192,9 +205,9 @@ template <int SP>
 void launch_batch2_sp(const BatchArgs& a, int blocks, hipStream_t s)
 {
     if (a.win_bytes)
-        hipLaunchKernelGGL((k_batch_step2<WinIOT<SP, true>>), dim3(blocks), dim3(TX, T2_WAVES), 0, s, a);
+        hipLaunchKernelGGL((k_batch_step2<WinIOT<SP, true>>), dim3(blocks), dim3(TX, B2_WAVES), 0, s, a);
     else
-        hipLaunchKernelGGL((k_batch_step2<BufIOT<SP>>), dim3(blocks), dim3(TX, T2_WAVES), 0, s, a);
+        hipLaunchKernelGGL((k_batch_step2<BufIOT<SP>>), dim3(blocks), dim3(TX, B2_WAVES), 0, s, a);
 }
 }  // namespace
 
@@ -212,8 +225,8 @@ hipError_t launch_batch_step2(const BatchArgs& a, int blocks, hipStream_t s)
 int batch_step2_tile(int* width, int* rows)
 {
     if (width) *width = T2_W;
-    if (rows) *rows = T2_ROWS;
-    return T2_WAVES;
+    if (rows) *rows = B2_WAVES - 2;
+    return B2_WAVES;
 }
 
 int batch_blocks_per_cu(int rows)
