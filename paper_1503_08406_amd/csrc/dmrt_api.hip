@@ -1378,20 +1378,29 @@ int cut_dies(const std::vector<long long>& w, int* die)
     return most;
 }
 
-// Tile list of the two-step kernel: tiles of T2_W x T2_ROWS nodes, row-major
-// inside each cavity, cavity by cavity; one block per tile.
+// Tile list of the two-step kernel, cavity by cavity, one block per tile:
+// wide tiles row-major, then, where a cavity's last column chunk is no wider
+// than a narrow tile, that column in narrow tiles (rows of 32 lanes: half
+// the idle lanes of a ragged last column).
 int batch_layout2(dmrt_batch* b)
 {
-    int tw = 0, th = 0;
-    dmrtk::batch_step2_tile(&tw, &th);
+    int tw = 0, th = 0, nw = 0, nh = 0;
+    dmrtk::batch_step2_tile(&tw, &th, &nw, &nh);
     std::vector<int4> tl;
     std::vector<long long> w;
     for (int c = 0; c < b->ncav; ++c) {
         const Geom& G = b->cav[c].G;
+        const int last = G.nx - (G.nx - 1) / tw * tw;  // width of the last column chunk
+        const int xw = last <= nw ? G.nx - last : G.nx;  // end of the wide tiles
         for (int y0 = 0; y0 < G.ny; y0 += th)
-            for (int x0 = 0; x0 < G.nx; x0 += tw) {
+            for (int x0 = 0; x0 < xw; x0 += tw) {
                 tl.push_back(make_int4(c, x0, y0, 0));
-                w.push_back((long long)std::min(tw, G.nx - x0) * std::min(th, G.ny - y0));
+                w.push_back((long long)std::min(tw, xw - x0) * std::min(th, G.ny - y0));
+            }
+        if (xw < G.nx)
+            for (int y0 = 0; y0 < G.ny; y0 += nh) {
+                tl.push_back(make_int4(c, xw, y0, 1));
+                w.push_back((long long)(G.nx - xw) * std::min(nh, G.ny - y0));
             }
     }
     const int most = cut_dies(w, b->die2);

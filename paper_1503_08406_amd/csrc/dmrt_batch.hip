@@ -86,10 +86,27 @@ void k_batch_step(BatchArgs a)
     }
 }
 
-// Waves of a two-step block in a batch: tiles of 62 x 10 nodes.  Taller
-// than the single lattice's (8 waves, 62 x 6): measured 1.9 % faster on the
-// 512-cavity workload (538.0 against 548.4 us per step) and even on batches
-// of 512^2 cavities; the single lattice's fast cases lose 8 % at 12 waves.
+// Position in a die's tile list of the die's j-th block (of n): the list in
+// groups of 32 consecutive tiles, group g rotated by g.  Blocks reach a
+// die's CUs in a fixed rotation, so with a tile list whose row length
+// shares a factor with 32 (8 tiles per cavity row, say) the same CUs would
+// always get the same tile column; the column at the hot wall, which holds
+// the liquid and the flow work, then lands on a few CUs.  Rotating each
+// group spreads it while neighbouring tiles stay within 32 list places
+// (measured on 64 cavities of 496 x 512: 179 -> 145 us per step; the
+// single lattice, whose rows of 17 or 67 tiles do not share the factor,
+// lost 3-4 % with the same rotation).
+__device__ __forceinline__ int rotated_tile(int j, int n)
+{
+    const int g = j >> 5, base = g << 5;
+    const int len = min(32, n - base);  // the last group may be shorter
+    return base + ((j & 31) + g % len) % len;
+}
+
+// Waves of a two-step block in a batch: tiles of 62 x 10 nodes (a narrow
+// last column of a cavity: 30 x 22).  Taller than the single lattice's (8
+// waves, 62 x 6): measured 3 % faster on the 512-cavity workload (531
+// against 548 us per step) and 2 % on batches of 512^2 cavities.
 #ifndef DMRT_B2_WAVES
 #define DMRT_B2_WAVES 12
 #endif
@@ -111,8 +128,10 @@ void k_batch_step2(BatchArgs a)
 {
     __shared__ float tl[TPLANES * B2_WAVES * TX];
     const int xcd = (int)(blockIdx.x & (NXCD - 1));
-    const int t = a.die[xcd] + (int)(blockIdx.x >> 3);
-    if (t >= a.die[xcd + 1]) return;  // the whole block: no barrier is left waiting
+    const int lo = a.die[xcd], n = a.die[xcd + 1] - lo;
+    const int j = (int)(blockIdx.x >> 3);
+    if (j >= n) return;  // the whole block: no barrier is left waiting
+    const int t = lo + rotated_tile(j, n);
     const int4 tile = load_uniform(a.tiles + t);
     const Cavity C = load_uniform(a.cav + tile.x);
     StepBufs B;
@@ -136,7 +155,10 @@ void k_batch_step2(BatchArgs a)
     A.eps_u = C.eps;
     A.Ac_u = C.Ac;
     A.Bc_u = C.Bc;
-    tile_step2<IO, true, B2_WAVES, true>(C.G, C.P, B, A, tile.y, tile.z, tl);
+    if (tile.w)  // a narrow last column: rows of 32 lanes
+        tile_step2<IO, true, B2_WAVES, true, false, TX / 2>(C.G, C.P, B, A, tile.y, tile.z, tl);
+    else
+        tile_step2<IO, true, B2_WAVES, true>(C.G, C.P, B, A, tile.y, tile.z, tl);
 }
 
 // Per-cavity partial counts (blockIdx.y = cavity): liquid nodes (f_l > 0)
@@ -222,10 +244,12 @@ hipError_t launch_batch_step2(const BatchArgs& a, int blocks, hipStream_t s)
     return hipGetLastError();
 }
 
-int batch_step2_tile(int* width, int* rows)
+int batch_step2_tile(int* width, int* rows, int* narrow_width, int* narrow_rows)
 {
     if (width) *width = T2_W;
     if (rows) *rows = B2_WAVES - 2;
+    if (narrow_width) *narrow_width = TX / 2 - 2;
+    if (narrow_rows) *narrow_rows = 2 * B2_WAVES - 2;
     return B2_WAVES;
 }
 

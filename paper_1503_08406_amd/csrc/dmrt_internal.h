@@ -162,7 +162,7 @@ hipError_t launch_batch_step(const BatchArgs& a, int rows, int blocks, hipStream
 // block per tile, `blocks` = 8 x the largest part of a die.
 hipError_t launch_batch_step2(const BatchArgs& a, int blocks, hipStream_t s);
 // Two-step tiles: pass-B width and rows; returns the waves of a block.
-int batch_step2_tile(int* width, int* rows);
+int batch_step2_tile(int* width, int* rows, int* narrow_width = nullptr, int* narrow_rows = nullptr);
 // Blocks of 64 x rows lanes that fit on one compute unit at once.
 int batch_blocks_per_cu(int rows);
 // Per-cavity partial counts of liquid nodes (f_l > 0) and of non-finite f_l

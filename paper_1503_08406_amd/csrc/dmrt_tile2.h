@@ -55,11 +55,11 @@ __device__ __forceinline__ bool axis_node(int& v, int n, int periodic)
     return true;
 }
 
-// Tile slots of the sources x - e_i (i = 0..8) of the pass-B node at `slot`;
-// a source behind a wall is the node's own slot.
+// Tile slots of the sources x - e_i (i = 0..8) of the pass-B node at `slot`
+// (R slots per tile row); a source behind a wall is the node's own slot.
+template <int R>
 __device__ __forceinline__ void tile_sources(const FlowWalls& W, int slot, int (&s)[9])
 {
-    constexpr int R = TX;  // slots per tile row
     s[0] = slot;
     s[1] = W.w[1] ? slot : slot - 1;
     s[2] = W.w[2] ? slot : slot - R;
@@ -72,25 +72,32 @@ __device__ __forceinline__ void tile_sources(const FlowWalls& W, int slot, int (
 }
 
 // Both steps of the tile at (x0, y0) for a block of 64 x NW lanes with the
-// LDS planes `tl` (TPLANES x NW x 64 floats).  USTAT: uniform porous fields
-// (A.eps_u, A.Ac_u, A.Bc_u) instead of the per-node planes.  MID: the tile's
-// state k+1 is also stored, through A1 (its output arrays), with the stores
-// of a single step.
-template <class IO, bool FLOW, int NW, bool USTAT, bool MID = false>
+// LDS planes `tl` (TPLANES x NW x 64 floats).  The lanes form rows of TWD:
+// 64 (a wavefront per row, a tile of 62 x (NW - 2) nodes) or 32 (a
+// wavefront spans two rows, a tile of 30 x (2 NW - 2) nodes, for a narrow
+// last column of a lattice).  USTAT: uniform porous fields (A.eps_u,
+// A.Ac_u, A.Bc_u) instead of the per-node planes.  MID: the tile's state
+// k+1 is also stored, through A1 (its output arrays), with the stores of a
+// single step.
+template <class IO, bool FLOW, int NW, bool USTAT, bool MID = false, int TWD = TX>
 __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const StepBufs& B,
                                            const Arrays<IO>& A, int x0, int y0, float* tl,
                                            const Arrays<IO>* A1 = nullptr)
 {
     using off_t = typename IO::off_t;
-    constexpr int PS = NW * TX;  // floats per plane
-    constexpr int RB = NW - 2;   // pass-B rows
+    static_assert(TWD == TX || TWD == TX / 2, "rows of 64 or 32 lanes");
+    constexpr int PS = NW * TX;        // floats per plane
+    constexpr int RB = PS / TWD - 2;   // pass-B rows
     const int yend = min(y0 + RB, G.ny);
     const off_t pb = A.pb;
-    const int lane = (int)threadIdx.x, w = (int)threadIdx.y;
-    const int slot = w * TX + lane;
+    // lane (column) and row of this thread in the tile's lane grid
+    const int tid = (int)threadIdx.y * TX + (int)threadIdx.x;
+    const int lane = TWD == TX ? (int)threadIdx.x : tid % TWD;
+    const int w = TWD == TX ? (int)threadIdx.y : tid / TWD;
+    const int slot = tid;
     // the lanes of the tile (pass B), where (xa, ya) below is (xb, yb)
     const int xb = x0 - 1 + lane, yb = y0 - 1 + w;
-    const bool vb = w >= 1 && w <= RB && lane >= 1 && lane <= T2_W && xb < G.nx && yb < yend;
+    const bool vb = w >= 1 && w <= RB && lane >= 1 && lane <= TWD - 2 && xb < G.nx && yb < yend;
 
     // ---- pass A: step k -> k+1 of the tile and its ring (rows y0-1 .. yend)
     int xa = x0 - 1 + lane, ya = y0 - 1 + w;
@@ -144,7 +151,7 @@ __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const S
     if (!vb) return;
     const FlowWalls W(G, xb, yb);
     int s[9];
-    tile_sources(W, slot, s);
+    tile_sources<TWD>(W, slot, s);
     const off_t o = ((off_t)yb * (off_t)G.pitch + (off_t)xb) * 4u;
     Node<IO> m;
     m.x = xb;
