@@ -11,20 +11,36 @@ namespace {
 // their ring of nodes and the rows they pull from) run on the same die.  The
 // tile of a block comes from host-computed constants (no division on the
 // device).
+// ILV: tile rows interleaved over the dies instead (die d takes rows d,
+// d + 8, d + 16, ...; G.st_ntiles then counts tile rows).  Contiguous runs
+// keep the rows two tiles share in one die's L2; on wide lattices, whose
+// tile rows overflow it anyway, the interleaved rows measured faster
+// (launch_io2 picks by tiles per row).
 // MID: the state k+1 is stored too, into the arrays of B1 (recorded runs).
 // With one buffer resource for all arrays (WinIOT) the kernel is compiled
 // for 7 waves per SIMD, which fits its scalar registers into 94 with the
 // same few spills as without the bound: measured 3-7 % faster than the
 // unbounded build (106 scalar registers), the liquid-started lattice
 // unchanged; a bound of 8 spills 33 and is slower where flow dominates.
-template <class IO, bool FLOW, int NW, bool MID>
+template <class IO, bool FLOW, int NW, bool MID, bool ILV>
 __global__ __launch_bounds__(TX * NW) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? 7 : 1)))
 void k_step2(Geom G, Phys P, StepBufs B, StepBufs B1)
 {
     __shared__ float tl[TPLANES * NW * TX];
     int x0, y0;
     // G's tiling constants are those of the tiles of this kernel
-    if (!step_tile_origin<NW - 2, T2_W>(G, x0, y0)) return;  // the whole block
+    if (ILV) {
+        const uint32_t b = blockIdx.x, d = b & (NXCD - 1), j = b >> 3;
+        const uint32_t hi = __umulhi(j, G.st_magic);
+        const uint32_t qd = (hi + ((j - hi) >> 1)) >> ((uint32_t)(G.st_shift - 1) & 31u);
+        const uint32_t rd = G.st_shift == 0 ? j : qd;  // the die's row of tiles
+        const uint32_t row = rd * NXCD + d;
+        if (row >= (uint32_t)G.st_ntiles) return;  // the whole block
+        x0 = (int)(j - rd * (uint32_t)G.st_tx) * T2_W;
+        y0 = (int)row * (NW - 2);
+    } else if (!step_tile_origin<NW - 2, T2_W>(G, x0, y0)) {
+        return;  // the whole block
+    }
     const Arrays<IO> A(G, B);
     if (MID) {
         const Arrays<IO> A1(G, B1);
@@ -41,11 +57,22 @@ hipError_t launch_io2(const Geom& G, const Phys& P, const StepBufs& B, const Ste
     constexpr int NW = T2_WAVES;
     Geom Gt = G;
     set_tiling(Gt, T2_W, NW - 2);
+    // rows interleaved over the dies from 48 tiles per row (lattices about
+    // 3000 nodes wide and more; measured at 1024-6144 nodes)
+    const bool ilv = Gt.st_tx >= 48;
+    if (ilv) {
+        Gt.st_ntiles /= Gt.st_tx;  // tile rows
+        Gt.st_per_xcd = (Gt.st_ntiles + NXCD - 1) / NXCD * Gt.st_tx;
+    }
     const dim3 grd(NXCD * Gt.st_per_xcd);
-    if (mid)
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);
+    if (mid && ilv)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);
+    else if (mid)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, false>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);
+    else if (ilv)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
     else
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, false>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
     return hipGetLastError();
 }
 

@@ -139,6 +139,36 @@ def test_per_array_addressing_gives_the_same_bits(oracle_mod, bc):
         _compare(s1, s3, "%s per array after %d" % (bc, s1.time))
 
 
+def test_two_steps_per_launch_on_a_wide_lattice_with_rows_interleaved_over_dies(oracle_mod):
+    """A lattice of 48 or more tiles per row (3000 nodes wide) takes the
+    launch that interleaves tile rows over the dies: random states and a
+    melting run give the bits of one step per launch, and a recorded run
+    (two-step launches that also store the state between) ends at the same
+    state."""
+    from paper_1503_08406_amd.dmrt import Solver
+    L = oracle_mod.lattice()
+    kinds, tw = BCS["box"]
+    case = W.make_case("wide", 3000, 37, kinds, tw, Ra=2e5, Da=2e-3, Pr=1.0, Ste=0.8, eps=0.45,
+                       H=37, T_init=0.4, T_s=0.38, T_l=0.42, convective=1)
+    f, g, fl = W.random_state(3000, 37, 13, L["w9"], L["w5"])
+    s1, s2 = _pair(case)
+    for s in (s1, s2):
+        s.set_state(f, g, fl)
+    for n in (2, 1, 4):
+        s1.step(n)
+        s2.step(n)
+        _compare(s1, s2, "wide after %d" % s1.time)
+    melt = W.cavity(nx=3000, ny=30, Ra=3e5, Da=5e-3, Ste=0.5, T_init=0.37)
+    s1, s2 = _pair(melt, graph_steps=8)
+    s3 = Solver(melt, record_mode=2)
+    s1.step(201)
+    s2.step(201)
+    s3.record(201)
+    _compare(s1, s2, "wide cavity")
+    _same(s1.fields(), s3.fields(), "wide cavity recorded")
+    assert (s1.fields()["fl"] > 0).sum() > 2 * 30  # past the wall column
+
+
 def test_launch_steps_reports_where_two_steps_apply():
     """Two steps per launch by default; one where the option, a literal
     variant of the thermal model, R2 or another launch shape rules it out
