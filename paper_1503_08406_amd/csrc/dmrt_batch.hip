@@ -86,23 +86,6 @@ void k_batch_step(BatchArgs a)
     }
 }
 
-// Position in a die's tile list of the die's j-th block (of n): the list in
-// groups of 32 consecutive tiles, group g rotated by g.  Blocks reach a
-// die's CUs in a fixed rotation, so with a tile list whose row length
-// shares a factor with 32 (8 tiles per cavity row, say) the same CUs would
-// always get the same tile column; the column at the hot wall, which holds
-// the liquid and the flow work, then lands on a few CUs.  Rotating each
-// group spreads it while neighbouring tiles stay within 32 list places
-// (measured on 64 cavities of 496 x 512: 179 -> 145 us per step; the
-// single lattice, whose rows of 17 or 67 tiles do not share the factor,
-// lost 3-4 % with the same rotation).
-__device__ __forceinline__ int rotated_tile(int j, int n)
-{
-    const int g = j >> 5, base = g << 5;
-    const int len = min(32, n - base);  // the last group may be shorter
-    return base + ((j & 31) + g % len) % len;
-}
-
 // Waves of a two-step block in a batch: tiles of 62 x 10 nodes (a narrow
 // last column of a cavity: 30 x 22).  Taller than the single lattice's (8
 // waves, 62 x 6): measured 3 % faster on the 512-cavity workload (531

@@ -15,22 +15,40 @@ namespace {
 // d + 8, d + 16, ...; G.st_ntiles then counts tile rows).  Contiguous runs
 // keep the rows two tiles share in one die's L2; on wide lattices, whose
 // tile rows overflow it anyway, the interleaved rows measured faster
-// (launch_io2 picks by tiles per row).
+// (launch_io2 picks by tiles per row).  ROT: each die's tiles taken in
+// the rotated groups of rotated_tile (rows of tiles a multiple of 8 long).
 // MID: the state k+1 is stored too, into the arrays of B1 (recorded runs).
 // With one buffer resource for all arrays (WinIOT) the kernel is compiled
 // for 7 waves per SIMD, which fits its scalar registers into 94 with the
 // same few spills as without the bound: measured 3-7 % faster than the
 // unbounded build (106 scalar registers), the liquid-started lattice
 // unchanged; a bound of 8 spills 33 and is slower where flow dominates.
-template <class IO, bool FLOW, int NW, bool MID, bool ILV>
+template <class IO, bool FLOW, int NW, bool MID, bool ILV, bool ROT = false>
 __global__ __launch_bounds__(TX * NW) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? 7 : 1)))
 void k_step2(Geom G, Phys P, StepBufs B, StepBufs B1)
 {
     __shared__ float tl[TPLANES * NW * TX];
     int x0, y0;
     // G's tiling constants are those of the tiles of this kernel
-    if (ILV) {
-        const uint32_t b = blockIdx.x, d = b & (NXCD - 1), j = b >> 3;
+    if (ROT && !ILV) {
+        const int d = (int)(blockIdx.x & (NXCD - 1)), first = d * G.st_per_xcd;
+        const int j = (int)(blockIdx.x >> 3), n = min(G.st_per_xcd, G.st_ntiles - first);
+        if (j >= n) return;  // the whole block
+        const uint32_t tile = (uint32_t)(first + rotated_tile(j, n));
+        const uint32_t hi = __umulhi(tile, G.st_magic);
+        const uint32_t qd = (hi + ((tile - hi) >> 1)) >> ((uint32_t)(G.st_shift - 1) & 31u);
+        const uint32_t q = G.st_shift == 0 ? tile : qd;
+        x0 = (int)(tile - q * (uint32_t)G.st_tx) * T2_W;
+        y0 = (int)q * (NW - 2);
+    } else if (ILV) {
+        const uint32_t b = blockIdx.x, d = b & (NXCD - 1);
+        uint32_t j = b >> 3;
+        if (ROT) {
+            // the die's rows d, d + 8, ...: a prefix of its index range
+            const int n = ((G.st_ntiles - (int)d + NXCD - 1) / NXCD) * G.st_tx;
+            if ((int)j >= n) return;  // the whole block
+            j = (uint32_t)rotated_tile((int)j, n);
+        }
         const uint32_t hi = __umulhi(j, G.st_magic);
         const uint32_t qd = (hi + ((j - hi) >> 1)) >> ((uint32_t)(G.st_shift - 1) & 31u);
         const uint32_t rd = G.st_shift == 0 ? j : qd;  // the die's row of tiles
@@ -65,7 +83,13 @@ hipError_t launch_io2(const Geom& G, const Phys& P, const StepBufs& B, const Ste
         Gt.st_per_xcd = (Gt.st_ntiles + NXCD - 1) / NXCD * Gt.st_tx;
     }
     const dim3 grd(NXCD * Gt.st_per_xcd);
-    if (mid && ilv)
+    // rows of tiles a multiple of 8 long: rotated groups (flow runs only)
+    const bool rot = FLOW && !mid && Gt.st_tx % 8 == 0;
+    if (rot && ilv)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, true, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
+    else if (rot)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, false, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
+    else if (mid && ilv)
         hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);
     else if (mid)
         hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, false>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);

@@ -169,6 +169,33 @@ def test_two_steps_per_launch_on_a_wide_lattice_with_rows_interleaved_over_dies(
     assert (s1.fields()["fl"] > 0).sum() > 2 * 30  # past the wall column
 
 
+@pytest.mark.parametrize("nx", [496, 3968])
+def test_two_steps_per_launch_with_rotated_tile_groups(oracle_mod, nx):
+    """Rows of tiles a multiple of 8 long (8 tiles: 496 nodes; 64 tiles:
+    3968 nodes, also with the rows interleaved over the dies) take each
+    die's tiles in rotated groups: random states and a melting run give the
+    bits of one step per launch."""
+    L = oracle_mod.lattice()
+    kinds, tw = BCS["walls_x"]
+    ny = 23
+    case = W.make_case("rot", nx, ny, kinds, tw, Ra=2e5, Da=2e-3, Pr=1.0, Ste=0.8, eps=0.45,
+                       H=ny, T_init=0.4, T_s=0.38, T_l=0.42, convective=1)
+    f, g, fl = W.random_state(nx, ny, 17, L["w9"], L["w5"])
+    s1, s2 = _pair(case)
+    for s in (s1, s2):
+        s.set_state(f, g, fl)
+    for n in (2, 1, 4):
+        _say("rotated groups", nx, n)
+        s1.step(n)
+        s2.step(n)
+        _compare(s1, s2, "rotated %d after %d" % (nx, s1.time))
+    melt = W.cavity(nx=nx, ny=30, Ra=3e5, Da=5e-3, Ste=0.5, T_init=0.37)
+    s1, s2 = _pair(melt, graph_steps=8)
+    s1.step(201)
+    s2.step(201)
+    _compare(s1, s2, "rotated cavity %d" % nx)
+
+
 def test_launch_steps_reports_where_two_steps_apply():
     """Two steps per launch by default; one where the option, a literal
     variant of the thermal model, R2 or another launch shape rules it out
