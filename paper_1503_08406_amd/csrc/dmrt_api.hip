@@ -134,6 +134,7 @@ void set_tiling(Geom& G, int w, int h)
     G.st_tx = (G.nx + w - 1) / w;
     G.st_ntiles = G.st_tx * ((G.ny + h - 1) / h);
     G.st_per_xcd = (G.st_ntiles + NXCD - 1) / NXCD;
+    G.st_rot = G.st_tx % 8 == 0 ? 1 : 0;
     const uint32_t d = (uint32_t)G.st_tx;
     if (d == 1) {
         G.st_magic = 0;

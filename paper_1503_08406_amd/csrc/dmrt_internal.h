@@ -61,6 +61,7 @@ struct Geom {
     int wide;           // 1: 64-bit addressing (arrays beyond a 4 GB window)
     int store;          // cache policy of the default step's stores (ST_*)
     int per_array;      // 1: the two-step kernel uses one buffer resource per array
+    int st_rot;         // 1: rows of st_tx tiles, a multiple of 8: rotated tile groups
 };
 
 // Device buffers of one step (deviation populations for f).

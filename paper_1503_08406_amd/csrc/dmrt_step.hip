@@ -32,7 +32,7 @@ __global__ __launch_bounds__(TX * TYB) void k_step(Geom G, Phys P, StepBufs B)
 {
     // a tile of 64 x (TYB * CPT) nodes
     int x0 = 0, y0 = 0;
-    const bool tile = step_tile_origin<TYB * CPT>(G, x0, y0);
+    const bool tile = step_tile_origin<TYB * CPT, TX, true>(G, x0, y0);
     const Arrays<IO> A(G, B);
     const int x = x0 + (int)threadIdx.x;
     if (CPT == 1) {
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(TX * TYB) void k_step_r2(Geom G, Phys P, StepBufs B
     B.r2f = (js & 1) ? R.r2b : R.r2a;
     B.r2_its = js + 1;
     int x0, y0;
-    if (!step_tile_origin<TYB>(G, x0, y0)) return;
+    if (!step_tile_origin<TYB, TX, true>(G, x0, y0)) return;
     const Arrays<IO> A(G, B);
     const int x = x0 + (int)threadIdx.x;
     __shared__ FlowStage<TX * TYB> S;

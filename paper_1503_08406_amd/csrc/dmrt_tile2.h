@@ -44,24 +44,6 @@ constexpr int T2_ROWS = T2_WAVES - 2;
 // TG + i - 1 (i = 1..4), f_l^{k+1}.
 enum { TF = 0, TRHO = 8, TG = 9, TFL = 13, TPLANES = 14 };
 
-// Position in a die's tile list of the die's j-th block (of n): the list in
-// groups of 32 consecutive tiles, group g rotated by g.  Blocks reach a
-// die's CUs in a fixed rotation, so with rows of tiles whose length shares
-// a factor of 8 or more with 32 (8 tiles per cavity row, say) the same CUs
-// would keep getting the same tile column; the column at the hot wall,
-// which holds the liquid and the flow work, then lands on a few CUs.
-// Rotating each group spreads it while neighbouring tiles stay within 32
-// list places (measured: 64 cavities of 496 x 512, 179 -> 145 us per step;
-// a 992-wide lattice, 10.3 -> 9.3 us per step).  Where rows do not share
-// the factor (17 or 67 tiles) the rotation cost 3-4 %, so it is used only
-// where they do.
-__device__ __forceinline__ int rotated_tile(int j, int n)
-{
-    const int g = j >> 5, base = g << 5;
-    const int len = min(32, n - base);  // the last group may be shorter
-    return base + ((j & 31) + g % len) % len;
-}
-
 // Coordinate of a pass-A node on an axis: wrapped on a periodic axis, out
 // of the lattice (false) behind a wall.
 __device__ __forceinline__ bool axis_node(int& v, int n, int periodic)
