@@ -275,7 +275,7 @@ template <bool FLOW, bool FIRST>
 __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
 {
     int x, y;
-    if (!tile_coords<TY>(G, x, y)) return;
+    if (!tile_coords_rotated<TY>(G, x, y)) return;
     const size_t pl = (size_t)G.plane;
     const size_t p = (size_t)G.pitch;
     const size_t c = (size_t)y * p + (size_t)x;
