@@ -550,7 +550,9 @@ def main():
                          "the workload's 100000, so that the window sees the melted, "
                          "convecting cavity)")
     ap.add_argument("--n", type=int, default=1024, help="lattice side")
-    ap.add_argument("--graph-steps", type=int, default=64)
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="steps per HIP graph in the timed window (0: plain launches, "
+                         "measured faster on the 1024^2 lattice)")
     ap.add_argument("--block-rows", type=int, default=0, help="step-kernel block rows (0: auto)")
     ap.add_argument("--cells-per-lane", type=int, default=0, help="nodes per lane (0: auto)")
     ap.add_argument("--steps-per-launch", type=int, default=2,
@@ -593,8 +595,9 @@ def main():
     torch.cuda.set_device(0)
     case = W.cavity(nx=args.n, ny=args.n, steps=args.start + args.warmup + args.steps,
                     T_init=args.T_init)
-    # graphs of at most the window's length (even), so that a short window is
-    # one graph replay like a long one, not plain launches
+    # plain launches by default: the host keeps ahead of 18 us launches, and
+    # a graph's kernels ran 4 % slower in 20-step windows, 0-1 % in 2000-step
+    # ones.  With --graph-steps, graphs of at most the window's length (even).
     gsteps = min(args.graph_steps, args.steps // 2 * 2)
     over = dict(graph_steps=gsteps, block_rows=args.block_rows, store_hint=args.store_hint,
                 cells_per_lane=args.cells_per_lane, steps_per_launch=args.steps_per_launch)
