@@ -104,8 +104,9 @@ constexpr int B2_WAVES = DMRT_B2_WAVES;
 // waves per SIMD (two 12-wave blocks per CU, as the LDS allows); at 8-wave
 // blocks and 7 waves per SIMD this took 94 scalar registers with 15 spilled
 // (106 with 23 spilled for BufIOT) and measured 4.6 % faster on the batch of
-// 512 cavities; without the bound 0.8 %, with a bound of 8 slower.
-template <class IO>
+// 512 cavities; without the bound 0.8 %, with a bound of 8 slower.  UT:
+// every cavity has uniform thermal properties (tile_step2).
+template <class IO, bool UT = false>
 __global__ __launch_bounds__(TX * B2_WAVES) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? DMRT_B2_OCC : 1)))
 void k_batch_step2(BatchArgs a)
 {
@@ -139,9 +140,9 @@ void k_batch_step2(BatchArgs a)
     A.Ac_u = C.Ac;
     A.Bc_u = C.Bc;
     if (tile.w)  // a narrow last column: rows of 32 lanes
-        tile_step2<IO, true, B2_WAVES, true, false, TX / 2>(C.G, C.P, B, A, tile.y, tile.z, tl);
+        tile_step2<IO, true, B2_WAVES, true, false, TX / 2, UT>(C.G, C.P, B, A, tile.y, tile.z, tl);
     else
-        tile_step2<IO, true, B2_WAVES, true>(C.G, C.P, B, A, tile.y, tile.z, tl);
+        tile_step2<IO, true, B2_WAVES, true, false, TX, UT>(C.G, C.P, B, A, tile.y, tile.z, tl);
 }
 
 // Per-cavity partial counts (blockIdx.y = cavity): liquid nodes (f_l > 0)
@@ -209,7 +210,9 @@ namespace {
 template <int SP>
 void launch_batch2_sp(const BatchArgs& a, int blocks, hipStream_t s)
 {
-    if (a.win_bytes)
+    if (a.win_bytes && a.uniform_thermal)
+        hipLaunchKernelGGL((k_batch_step2<WinIOT<SP, true>, true>), dim3(blocks), dim3(TX, B2_WAVES), 0, s, a);
+    else if (a.win_bytes)
         hipLaunchKernelGGL((k_batch_step2<WinIOT<SP, true>>), dim3(blocks), dim3(TX, B2_WAVES), 0, s, a);
     else
         hipLaunchKernelGGL((k_batch_step2<BufIOT<SP>>), dim3(blocks), dim3(TX, B2_WAVES), 0, s, a);

@@ -325,11 +325,13 @@ __device__ __forceinline__ float ke_ratio(const Phys& P, float phi, float fl)
 
 // zeta_alpha = 1/tau_T(f_l) with tau_T = 1/2 + alpha_e(f_l)/(sigma c_sT^2);
 // alpha_e = lambda alpha(f_l), linear between the phases, or alpha_l k_e /
-// k_l (Eq. 8) with the node's porosity eps.
-template <bool VAR>
+// k_l (Eq. 8) with the node's porosity eps.  UT: compiled for uniform
+// thermal properties (P.zeta_uniform set, sigma_s = sigma_l), which the
+// launch has checked.
+template <bool VAR, bool UT = false>
 __device__ __forceinline__ float zeta_alpha(const Phys& P, float fl, float isig, float eps)
 {
-    if (P.zeta_uniform) return P.zeta_a;
+    if (UT || P.zeta_uniform) return P.zeta_a;
     if (VAR && P.ke_mode)
         return frcp(0.5f + P.alpha_l * ke_ratio(P, eps, fl) * isig * P.inv_csT2);
     return frcp(0.5f + (P.lam_as + fl * P.dlam) * isig * P.inv_csT2);
@@ -337,7 +339,7 @@ __device__ __forceinline__ float zeta_alpha(const Phys& P, float fl, float isig,
 
 // D2Q5 MRT collision (Eqs. 32, 34, 35, 37) with temperature T1 and
 // 1/sigma = isig at a node of porosity eps.
-template <bool VAR>
+template <bool VAR, bool UT = false>
 __device__ __forceinline__ void thermal_collide(float (&g)[5], float fl1, float isig, float T1,
                                                 float ux, float uy, float eps, const Phys& P)
 {
@@ -345,7 +347,7 @@ __device__ __forceinline__ void thermal_collide(float (&g)[5], float fl1, float 
     const float s13 = g[1] + g[3], s24 = g[2] + g[4];
     const float n3 = (s13 + s24) - 4.0f * g[0];
     const float n4 = s13 - s24;
-    const float za = zeta_alpha<VAR>(P, fl1, isig, eps);
+    const float za = zeta_alpha<VAR, UT>(P, fl1, isig, eps);
     const float ct = P.conv * T1 * isig;
     const float D1 = za * (n1 - ct * ux), D2 = za * (n2 - ct * uy);
     const float D3 = P.zeta_e * (n3 - P.varpi * T1), D4 = P.zeta_nu * n4;

@@ -154,6 +154,7 @@ struct BatchArgs {
     const char* win;
     const char* wout;
     uint32_t win_bytes;
+    int uniform_thermal;  // 1: every cavity has sigma_s = sigma_l and one tau_T
 };
 
 // Persistent batched step: `blocks` blocks (a multiple of 8) of 64 x rows

@@ -169,7 +169,7 @@ __device__ __forceinline__ float latent_S0(const Phys& P, float eps, float fk, f
 //   TM_R2: f_l^{k+1} of every node is given (B.r2f); each pulled g_i
 //     receives w~_i S~_0 of its pre-stream site x - e_i (Eq. 30; the node
 //     itself for i = 0 and behind a wall).
-template <class IO, bool FLOW, bool COUNT, int TM = TM_DEFAULT>
+template <class IO, bool FLOW, bool COUNT, int TM = TM_DEFAULT, bool UT = false>
 __device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, const StepBufs& B,
                                               const Arrays<IO>& A, Node<IO>& n, float& T1,
                                               float& fl1, float& isig1)
@@ -225,7 +225,7 @@ __device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, cons
             f = fn;
             if (done) break;
         }
-    } else if (P.dsig == 0.0f) {
+    } else if (UT || P.dsig == 0.0f) {
         const float a = alat * P.isig_s;
         for (;;) {
             ++it;
@@ -247,7 +247,7 @@ __device__ __forceinline__ void node_enthalpy(const Geom& G, const Phys& P, cons
     }
     fl1 = f;
     isig1 = (VAR && P.sig_mode) ? frcp(sg0 + fl1 * dsg)
-                                : P.dsig == 0.0f ? P.isig_s : frcp(P.sig_s + fl1 * P.dsig);
+                                : (UT || P.dsig == 0.0f) ? P.isig_s : frcp(P.sig_s + fl1 * P.dsig);
     const float dT = -alat * (fl1 - flk) * isig1;  // S~_0 (Eq. 38)
     T1 = Tstar + dT;
     g[0] += P.w5_0 * dT;

@@ -18,12 +18,15 @@ namespace {
 // (launch_io2 picks by tiles per row).  ROT: each die's tiles taken in
 // the rotated groups of rotated_tile (rows of tiles a multiple of 8 long).
 // MID: the state k+1 is stored too, into the arrays of B1 (recorded runs).
+// UT: compiled for uniform thermal properties (sigma_s = sigma_l and one
+// tau_T; launch_io2 checks them), without the per-node relaxation rate and
+// 1/sigma of the general case: the same values, fewer instructions.
 // With one buffer resource for all arrays (WinIOT) the kernel is compiled
 // for 7 waves per SIMD, which fits its scalar registers into 94 with the
 // same few spills as without the bound: measured 3-7 % faster than the
 // unbounded build (106 scalar registers), the liquid-started lattice
 // unchanged; a bound of 8 spills 33 and is slower where flow dominates.
-template <class IO, bool FLOW, int NW, bool MID, bool ILV, bool ROT = false>
+template <class IO, bool FLOW, int NW, bool MID, bool ILV, bool ROT = false, bool UT = false>
 __global__ __launch_bounds__(TX * NW) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? 7 : 1)))
 void k_step2(Geom G, Phys P, StepBufs B, StepBufs B1)
 {
@@ -62,19 +65,39 @@ void k_step2(Geom G, Phys P, StepBufs B, StepBufs B1)
     const Arrays<IO> A(G, B);
     if (MID) {
         const Arrays<IO> A1(G, B1);
-        tile_step2<IO, FLOW, NW, false, true>(G, P, B, A, x0, y0, tl, &A1);
+        tile_step2<IO, FLOW, NW, false, true, TX, UT>(G, P, B, A, x0, y0, tl, &A1);
     } else {
-        tile_step2<IO, FLOW, NW, false>(G, P, B, A, x0, y0, tl);
+        tile_step2<IO, FLOW, NW, false, false, TX, UT>(G, P, B, A, x0, y0, tl);
     }
+}
+
+template <class IO, bool FLOW, bool UT>
+hipError_t launch_tiles2(const Geom& Gt, const Phys& P, const StepBufs& B, const StepBufs* mid,
+                         bool ilv, bool rot, hipStream_t s)
+{
+    constexpr int NW = T2_WAVES;
+    const dim3 grd(NXCD * Gt.st_per_xcd), blk(TX, NW);
+    if (rot && ilv)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, true, true, UT>), grd, blk, 0, s, Gt, P, B, B);
+    else if (rot)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, false, true, UT>), grd, blk, 0, s, Gt, P, B, B);
+    else if (mid && ilv)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, true, false, UT>), grd, blk, 0, s, Gt, P, B, *mid);
+    else if (mid)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, false, false, UT>), grd, blk, 0, s, Gt, P, B, *mid);
+    else if (ilv)
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, true, false, UT>), grd, blk, 0, s, Gt, P, B, B);
+    else
+        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, false, false, UT>), grd, blk, 0, s, Gt, P, B, B);
+    return hipGetLastError();
 }
 
 template <class IO, bool FLOW>
 hipError_t launch_io2(const Geom& G, const Phys& P, const StepBufs& B, const StepBufs* mid,
                       hipStream_t s)
 {
-    constexpr int NW = T2_WAVES;
     Geom Gt = G;
-    set_tiling(Gt, T2_W, NW - 2);
+    set_tiling(Gt, T2_W, T2_WAVES - 2);
     // rows interleaved over the dies from 48 tiles per row (lattices about
     // 3000 nodes wide and more; measured at 1024-6144 nodes)
     const bool ilv = Gt.st_tx >= 48;
@@ -82,22 +105,11 @@ hipError_t launch_io2(const Geom& G, const Phys& P, const StepBufs& B, const Ste
         Gt.st_ntiles /= Gt.st_tx;  // tile rows
         Gt.st_per_xcd = (Gt.st_ntiles + NXCD - 1) / NXCD * Gt.st_tx;
     }
-    const dim3 grd(NXCD * Gt.st_per_xcd);
     // rows of tiles a multiple of 8 long: rotated groups (flow runs only)
     const bool rot = FLOW && !mid && Gt.st_tx % 8 == 0;
-    if (rot && ilv)
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, true, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
-    else if (rot)
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, false, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
-    else if (mid && ilv)
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);
-    else if (mid)
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, true, false>), grd, dim3(TX, NW), 0, s, Gt, P, B, *mid);
-    else if (ilv)
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, true>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
-    else
-        hipLaunchKernelGGL((k_step2<IO, FLOW, NW, false, false>), grd, dim3(TX, NW), 0, s, Gt, P, B, B);
-    return hipGetLastError();
+    if (P.zeta_uniform && P.dsig == 0.0f)
+        return launch_tiles2<IO, FLOW, true>(Gt, P, B, mid, ilv, rot, s);
+    return launch_tiles2<IO, FLOW, false>(Gt, P, B, mid, ilv, rot, s);
 }
 
 }  // namespace

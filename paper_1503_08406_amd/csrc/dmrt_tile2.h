@@ -78,8 +78,8 @@ __device__ __forceinline__ void tile_sources(const FlowWalls& W, int slot, int (
 // last column of a lattice).  USTAT: uniform porous fields (A.eps_u,
 // A.Ac_u, A.Bc_u) instead of the per-node planes.  MID: the tile's state
 // k+1 is also stored, through A1 (its output arrays), with the stores of a
-// single step.
-template <class IO, bool FLOW, int NW, bool USTAT, bool MID = false, int TWD = TX>
+// single step.  UT: compiled for uniform thermal properties (zeta_alpha).
+template <class IO, bool FLOW, int NW, bool USTAT, bool MID = false, int TWD = TX, bool UT = false>
 __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const StepBufs& B,
                                            const Arrays<IO>& A, int x0, int y0, float* tl,
                                            const Arrays<IO>* A1 = nullptr)
@@ -114,7 +114,7 @@ __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const S
     if (va) {
         node_load<IO, FLOW, USTAT>(G, A, xa, ya, n);
         __builtin_amdgcn_s_setprio(0);
-        node_enthalpy<IO, FLOW, false>(G, P, B, A, n, T1, fl1, isig1);
+        node_enthalpy<IO, FLOW, false, TM_DEFAULT, UT>(G, P, B, A, n, T1, fl1, isig1);
         if (FLOW && fl1 > 0.0f) {
             float d[9];
             off_t o;
@@ -132,7 +132,7 @@ __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const S
                 A1->uv.st(o, pb, uy);
             }
         }
-        thermal_collide<false>(n.g, fl1, isig1, T1, ux, uy, n.eps, P);
+        thermal_collide<false, UT>(n.g, fl1, isig1, T1, ux, uy, n.eps, P);
 #pragma unroll
         for (int i = 1; i < 5; ++i) tl[(TG + i - 1) * PS + slot] = n.g[i];
         tl[TFL * PS + slot] = fl1;
@@ -170,7 +170,7 @@ __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const S
         }
     }
     float T2, fl2, isig2, vx = 0.0f, vy = 0.0f;
-    node_enthalpy<IO, FLOW, false>(G, P, B, A, m, T2, fl2, isig2);
+    node_enthalpy<IO, FLOW, false, TM_DEFAULT, UT>(G, P, B, A, m, T2, fl2, isig2);
     if (FLOW && fl2 > 0.0f) {
         float d[9];
         if (fl1 > 0.0f) {
@@ -204,7 +204,7 @@ __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const S
         A.uv.st(o, 0, vx);
         A.uv.st(o, pb, vy);
     }
-    thermal_collide<false>(m.g, fl2, isig2, T2, vx, vy, m.eps, P);
+    thermal_collide<false, UT>(m.g, fl2, isig2, T2, vx, vy, m.eps, P);
 #pragma unroll
     for (int i = 0; i < 5; ++i) A.gout.st(o, (off_t)i * pb, m.g[i]);
     A.flout.st(o, 0, fl2);
