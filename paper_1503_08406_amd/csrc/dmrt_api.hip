@@ -1489,7 +1489,8 @@ dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p, bool two = false)
     a.win_bytes = !b->per_array && half < (1ull << 32) ? (uint32_t)half : 0u;
     a.uniform_thermal = 1;
     for (const dmrtk::Cavity& c : b->cav)
-        if (!c.P.zeta_uniform || c.P.dsig != 0.0f) a.uniform_thermal = 0;
+        if (!c.P.zeta_uniform || c.P.dsig != 0.0f || c.G.per_x || c.G.per_y)
+            a.uniform_thermal = 0;
     return a;
 }
 

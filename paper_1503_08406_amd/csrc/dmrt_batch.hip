@@ -105,7 +105,8 @@ constexpr int B2_WAVES = DMRT_B2_WAVES;
 // blocks and 7 waves per SIMD this took 94 scalar registers with 15 spilled
 // (106 with 23 spilled for BufIOT) and measured 4.6 % faster on the batch of
 // 512 cavities; without the bound 0.8 %, with a bound of 8 slower.  UT:
-// every cavity has uniform thermal properties (tile_step2).
+// every cavity has the cavity form of tile_step2 (uniform thermal
+// properties, walls on every side).
 template <class IO, bool UT = false>
 __global__ __launch_bounds__(TX * B2_WAVES) __attribute__((amdgpu_waves_per_eu(InWindow<IO>::value ? DMRT_B2_OCC : 1)))
 void k_batch_step2(BatchArgs a)

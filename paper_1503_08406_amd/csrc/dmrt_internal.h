@@ -154,7 +154,8 @@ struct BatchArgs {
     const char* win;
     const char* wout;
     uint32_t win_bytes;
-    int uniform_thermal;  // 1: every cavity has sigma_s = sigma_l and one tau_T
+    int uniform_thermal;  // 1: every cavity has sigma_s = sigma_l, one tau_T and walls
+                          // on every side
 };
 
 // Persistent batched step: `blocks` blocks (a multiple of 8) of 64 x rows

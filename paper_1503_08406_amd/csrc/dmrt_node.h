@@ -66,14 +66,30 @@ struct Node {
 // Byte offsets of node (x, y) and of its axis sources x - e_i, and the
 // wrapped neighbour indices, without branches: periodic axes wrap; a source
 // behind a wall is pointed at the node itself (always in bounds) and its
-// value is replaced later, so every pull is an unconditional load.
-template <class IO>
+// value is replaced later, so every pull is an unconditional load.  WALLED:
+// compiled for a lattice with walls on every side (no periodic axis), whose
+// neighbours are the node's offset plus or minus one column or row.
+template <class IO, bool WALLED = false>
 __device__ __forceinline__ void node_geometry(const Geom& G, int x, int y, Node<IO>& n)
 {
     using off_t = typename IO::off_t;
     n.x = x;
     n.y = y;
     const bool xlo = x == 0, xhi = x == G.nx - 1, ylo = y == 0, yhi = y == G.ny - 1;
+    if constexpr (WALLED) {
+        const off_t row = (off_t)G.pitch * 4u;
+        const off_t o = ((off_t)y * (off_t)G.pitch + (off_t)x) * 4u;
+        n.o = o;
+        n.o1 = xlo ? o : o - 4u;
+        n.o3 = xhi ? o : o + 4u;
+        n.o2 = ylo ? o : o - row;
+        n.o4 = yhi ? o : o + row;
+        n.xm = x - 1;
+        n.xp = x + 1;
+        n.ym = y - 1;
+        n.yp = y + 1;
+        return;
+    }
     const bool wxm = xlo & !G.per_x, wxp = xhi & !G.per_x;
     const bool wym = ylo & !G.per_y, wyp = yhi & !G.per_y;
     const int xm = xlo ? G.nx - 1 : x - 1, xp = xhi ? 0 : x + 1;
@@ -95,12 +111,12 @@ __device__ __forceinline__ void node_geometry(const Geom& G, int x, int y, Node<
 // First load batch of node (x, y): f_l^k, porosity and the five g pulls
 // (every node needs them, liquid or solid); a wall node also loads its own
 // g+_1..4 and u^k for the extrapolation at the wall, in the same batch.
-template <class IO, bool FLOW, bool USTAT = false>
+template <class IO, bool FLOW, bool USTAT = false, bool WALLED = false>
 __device__ __forceinline__ void node_load(const Geom& G, const Arrays<IO>& A, int x, int y,
                                           Node<IO>& n)
 {
     using off_t = typename IO::off_t;
-    node_geometry(G, x, y, n);
+    node_geometry<IO, WALLED>(G, x, y, n);
     const off_t pb = A.pb, o = n.o;
     n.flk = A.flin.ld(o, 0);
     n.eps = USTAT ? A.eps_u : A.stat.ld(o, 0);
@@ -351,7 +367,7 @@ __device__ __forceinline__ float rho_dev(const float (&d)[9])
 // node is issued in one batch; values are selected afterwards, so no load
 // waits behind a data-dependent branch.  The node's drag coefficients are
 // handed back for a second step of the same node.
-template <class IO, bool USTAT>
+template <class IO, bool USTAT, bool WALLED = false>
 __device__ __forceinline__ void node_flow_core(const Geom& G, const Phys& P, const Arrays<IO>& A,
                                                int x, int y, float flk, float fl1, float T1,
                                                float eps, float (&d)[9], float& ux, float& uy,
@@ -362,15 +378,24 @@ __device__ __forceinline__ void node_flow_core(const Geom& G, const Phys& P, con
     const off_t pb = A.pb;
     const IO &fin = A.fin, &flin = A.flin;
     Node<IO> n;
-    node_geometry(G, x, y, n);
+    node_geometry<IO, WALLED>(G, x, y, n);
     const off_t o = n.o, o1 = n.o1, o2 = n.o2, o3 = n.o3, o4 = n.o4;
     const FlowWalls W(G, x, y);
-    const off_t pitch = (off_t)G.pitch;
-    const off_t rm = (off_t)n.ym * pitch, rp = (off_t)n.yp * pitch;
-    const off_t o5 = W.w[5] ? o : (rm + (off_t)n.xm) * 4u;
-    const off_t o6 = W.w[6] ? o : (rm + (off_t)n.xp) * 4u;
-    const off_t o7 = W.w[7] ? o : (rp + (off_t)n.xp) * 4u;
-    const off_t o8 = W.w[8] ? o : (rp + (off_t)n.xm) * 4u;
+    off_t o5, o6, o7, o8;
+    if constexpr (WALLED) {
+        const off_t row = (off_t)G.pitch * 4u;
+        o5 = W.w[5] ? o : o - row - 4u;
+        o6 = W.w[6] ? o : o - row + 4u;
+        o7 = W.w[7] ? o : o + row + 4u;
+        o8 = W.w[8] ? o : o + row - 4u;
+    } else {
+        const off_t pitch = (off_t)G.pitch;
+        const off_t rm = (off_t)n.ym * pitch, rp = (off_t)n.yp * pitch;
+        o5 = W.w[5] ? o : (rm + (off_t)n.xm) * 4u;
+        o6 = W.w[6] ? o : (rm + (off_t)n.xp) * 4u;
+        o7 = W.w[7] ? o : (rp + (off_t)n.xp) * 4u;
+        o8 = W.w[8] ? o : (rp + (off_t)n.xm) * 4u;
+    }
     const float Ac = USTAT ? A.Ac_u : A.stat.ld(o, pb);
     const float Bc = USTAT ? A.Bc_u : A.stat.ld(o, 2 * pb);
     o_out = o;

@@ -18,9 +18,11 @@ namespace {
 // (launch_io2 picks by tiles per row).  ROT: each die's tiles taken in
 // the rotated groups of rotated_tile (rows of tiles a multiple of 8 long).
 // MID: the state k+1 is stored too, into the arrays of B1 (recorded runs).
-// UT: compiled for uniform thermal properties (sigma_s = sigma_l and one
-// tau_T; launch_io2 checks them), without the per-node relaxation rate and
-// 1/sigma of the general case: the same values, fewer instructions.
+// UT: compiled for the cavity form (launch_io2 checks it): uniform thermal
+// properties (sigma_s = sigma_l and one tau_T), without the per-node
+// relaxation rate and 1/sigma of the general case, and walls on every side,
+// with neighbour offsets one column or row away: the same values, fewer
+// instructions.
 // With one buffer resource for all arrays (WinIOT) the kernel is compiled
 // for 7 waves per SIMD, which fits its scalar registers into 94 with the
 // same few spills as without the bound: measured 3-7 % faster than the
@@ -107,7 +109,7 @@ hipError_t launch_io2(const Geom& G, const Phys& P, const StepBufs& B, const Ste
     }
     // rows of tiles a multiple of 8 long: rotated groups (flow runs only)
     const bool rot = FLOW && !mid && Gt.st_tx % 8 == 0;
-    if (P.zeta_uniform && P.dsig == 0.0f)
+    if (P.zeta_uniform && P.dsig == 0.0f && !G.per_x && !G.per_y)
         return launch_tiles2<IO, FLOW, true>(Gt, P, B, mid, ilv, rot, s);
     return launch_tiles2<IO, FLOW, false>(Gt, P, B, mid, ilv, rot, s);
 }

@@ -78,7 +78,8 @@ __device__ __forceinline__ void tile_sources(const FlowWalls& W, int slot, int (
 // last column of a lattice).  USTAT: uniform porous fields (A.eps_u,
 // A.Ac_u, A.Bc_u) instead of the per-node planes.  MID: the tile's state
 // k+1 is also stored, through A1 (its output arrays), with the stores of a
-// single step.  UT: compiled for uniform thermal properties (zeta_alpha).
+// single step.  UT: compiled for the cavity form, uniform thermal
+// properties (zeta_alpha) and walls on every side (node_geometry).
 template <class IO, bool FLOW, int NW, bool USTAT, bool MID = false, int TWD = TX, bool UT = false>
 __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const StepBufs& B,
                                            const Arrays<IO>& A, int x0, int y0, float* tl,
@@ -112,13 +113,13 @@ __device__ __forceinline__ void tile_step2(const Geom& G, const Phys& P, const S
     // first load batch at raised wave priority (as in block_step)
     __builtin_amdgcn_s_setprio(2);
     if (va) {
-        node_load<IO, FLOW, USTAT>(G, A, xa, ya, n);
+        node_load<IO, FLOW, USTAT, UT>(G, A, xa, ya, n);
         __builtin_amdgcn_s_setprio(0);
         node_enthalpy<IO, FLOW, false, TM_DEFAULT, UT>(G, P, B, A, n, T1, fl1, isig1);
         if (FLOW && fl1 > 0.0f) {
             float d[9];
             off_t o;
-            node_flow_core<IO, USTAT>(G, P, A, xa, ya, n.flk, fl1, T1, n.eps, d, ux, uy, o, Ac,
+            node_flow_core<IO, USTAT, UT>(G, P, A, xa, ya, n.flk, fl1, T1, n.eps, d, ux, uy, o, Ac,
                                       Bc);
 #pragma unroll
             for (int i = 1; i < 9; ++i) tl[(TF + i - 1) * PS + slot] = d[i];
