@@ -20,6 +20,8 @@
 // collision, the latent source and enthalpy update and the wall/interface
 // extrapolations, and writes the local adjoints of step k (the adjoints of
 // its pulled inputs and of its own state) for the next launch.
+#include <type_traits>
+
 #include "dmrt_device.h"
 
 namespace dmrtk {
@@ -171,6 +173,24 @@ __device__ __forceinline__ void flow_collide_adj(const float (&d)[9], float fl1,
 // where the node was liquid at k+1, and a node's flow local adjoints only
 // where it was liquid at k+2.  L: d+ (0..8), rho - 1 (9), g+ (10..14),
 // f_l (15), u (16, 17).
+// An array of the reversed step.  O32: every element index of the launch
+// is below 2^30, and an access adds a 32-bit byte offset to the array's
+// base (the load takes the base from scalar registers); else 64-bit
+// indices.
+template <class T, bool O32>
+struct AdjArr {
+    T* p;
+    __device__ __forceinline__ T& operator[](size_t i) const
+    {
+        if constexpr (O32) {
+            using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+            return *reinterpret_cast<T*>(reinterpret_cast<C*>(p) + ((uint32_t)i << 2));
+        } else {
+            return p[i];
+        }
+    }
+};
+
 // Receivers y + e_i of node (x, y) (rc) and whether each exists (ok).
 __device__ __forceinline__ void gather_receivers(const Geom& G, int x, int y, bool (&ok)[9],
                                                  size_t (&rc)[9])
@@ -204,7 +224,8 @@ __device__ __forceinline__ void gather_receivers(const Geom& G, int x, int y, bo
 // The thermal terms of gather_state, loaded with the node's first batch:
 // own g terms (0..4), own f_l (5), the receivers' g pulls (6..9; loaded from
 // in-lattice addresses even where a receiver is absent).
-__device__ __forceinline__ void gather_thermal_loads(const Geom& G, const float* __restrict__ la,
+template <bool O32>
+__device__ __forceinline__ void gather_thermal_loads(const Geom& G, AdjArr<const float, O32> la,
                                                      int x, int y, float (&t)[10])
 {
     const size_t pl = (size_t)G.plane;
@@ -219,9 +240,9 @@ __device__ __forceinline__ void gather_thermal_loads(const Geom& G, const float*
     for (int i = 1; i < 5; ++i) t[5 + i] = la[i * pl + rc[i]];
 }
 
-template <bool FLOW>
-__device__ __forceinline__ void gather_state(const Geom& G, const float* __restrict__ la,
-                                             float flA, const float* __restrict__ flB, int x,
+template <bool FLOW, bool O32>
+__device__ __forceinline__ void gather_state(const Geom& G, AdjArr<const float, O32> la,
+                                             float flA, AdjArr<const float, O32> flB, int x,
                                              int y, const float (&t)[10], float (&L)[ADJ_LS])
 {
     const size_t pl = (size_t)G.plane;
@@ -271,11 +292,15 @@ __device__ __forceinline__ void gather_state(const Geom& G, const float* __restr
 // One reversed step k+1 -> k for one node: the adjoint of its state at
 // k+1 (the terminal adjoint when FIRST, else gathered from the local
 // adjoints of step k+1), then the local adjoint of its step k.
-template <bool FLOW, bool FIRST>
+template <bool FLOW, bool FIRST, bool O32>
 __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
 {
     int x, y;
     if (!tile_coords_rotated<TY>(G, x, y)) return;
+    using CA = AdjArr<const float, O32>;
+    const CA aF0{B.f0}, aG0{B.g0}, aFL0{B.fl0}, aU0{B.u0}, aFL1{B.fl1}, aEPS{B.eps}, aAC{B.Ac},
+        aBC{B.Bc}, aFL2{B.fl2}, aLS{B.ls}, aLAP{B.la_prev};
+    const AdjArr<float, O32> aLA{B.la}, aGA{B.ga};
     const size_t pl = (size_t)G.plane;
     const size_t p = (size_t)G.pitch;
     const size_t c = (size_t)y * p + (size_t)x;
@@ -311,23 +336,23 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
 
     // ---- first load batch: every value whose address is known now (the
     // flow values follow in a second batch where the node is liquid)
-    const float flk = B.fl0[c], fl1 = B.fl1[c];
+    const float flk = aFL0[c], fl1 = aFL1[c];
     float t[10];  // thermal terms of the state adjoint (gather_state)
     float Ls[ADJ_LS];
     if (FIRST) {
 #pragma unroll
-        for (int i = 0; i < ADJ_LS; ++i) Ls[i] = B.ls[i * pl + c];
+        for (int i = 0; i < ADJ_LS; ++i) Ls[i] = aLS[i * pl + c];
     } else {
-        gather_thermal_loads(G, B.la_prev, x, y, t);
+        gather_thermal_loads<O32>(G, aLAP, x, y, t);
     }
-    const float eps = B.eps[c], Ac = B.Ac[c], Bc = B.Bc[c];
+    const float eps = aEPS[c], Ac = aAC[c], Bc = aBC[c];
     float q[5], g[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) q[i] = B.g0[i * pl + c];
+    for (int i = 0; i < 5; ++i) q[i] = aG0[i * pl + c];
     g[0] = q[0];
 #pragma unroll
-    for (int i = 1; i < 5; ++i) g[i] = B.g0[i * pl + src[i]];
-    const float u0x = FLOW ? B.u0[c] : 0.0f, u0y = FLOW ? B.u0[pl + c] : 0.0f;
+    for (int i = 1; i < 5; ++i) g[i] = aG0[i * pl + src[i]];
+    const float u0x = FLOW ? aU0[c] : 0.0f, u0y = FLOW ? aU0[pl + c] : 0.0f;
     const bool liqk = FLOW && flk > 0.0f;
     const bool liq1 = FLOW && fl1 > 0.0f;
 
@@ -362,13 +387,13 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
         float nf[9];
         nf[0] = 0.0f;
 #pragma unroll
-        for (int i = 1; i < 9; ++i) nf[i] = B.fl0[src[i]];
+        for (int i = 1; i < 9; ++i) nf[i] = aFL0[src[i]];
         if (liqk) {
             float v[17];  // own f+_0..8 (0..8), pulls 1..8 (9..16)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) v[i] = B.f0[i * pl + c];
+            for (int i = 0; i < 9; ++i) v[i] = aF0[i * pl + c];
 #pragma unroll
-            for (int i = 1; i < 9; ++i) v[8 + i] = B.f0[i * pl + src[i]];
+            for (int i = 1; i < 9; ++i) v[8 + i] = aF0[i * pl + src[i]];
             pin_loads(nf);
             pin_loads(v);
 #pragma unroll
@@ -386,7 +411,7 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
             float nr[9];
             nr[0] = 0.0f;
 #pragma unroll
-            for (int k = 1; k < 9; ++k) nr[k] = B.f0[9 * pl + src[k]];
+            for (int k = 1; k < 9; ++k) nr[k] = aF0[9 * pl + src[k]];
             pin_loads(nf);
             pin_loads(nr);
             float rsum = 0.0f;
@@ -411,11 +436,11 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
     // this node only) ride with the flow batch of the gather
     float ga0 = 0.0f, ga1 = 0.0f, ga2 = 0.0f;
     if (liq1) {
-        ga0 = B.ga[c];
-        ga1 = B.ga[pl + c];
-        ga2 = B.ga[2 * pl + c];
+        ga0 = aGA[c];
+        ga1 = aGA[pl + c];
+        ga2 = aGA[2 * pl + c];
     }
-    if (!FIRST) gather_state<FLOW>(G, B.la_prev, fl1, B.fl2, x, y, t, Ls);
+    if (!FIRST) gather_state<FLOW, O32>(G, aLAP, fl1, aFL2, x, y, t, Ls);
 
     // ---- reverse: thermal collision (uniform zeta)
     float Lg[5];
@@ -545,11 +570,11 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
 
     // ---- outputs (a node solid at k+1 reads its porosity accumulator here)
     const bool acc_eps = Leps != 0.0f;
-    if (acc_eps && !liq1) ga0 = B.ga[c];
+    if (acc_eps && !liq1) ga0 = aGA[c];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        B.la[i * pl + c] = Lgp[i];
-        B.la[(15 + i) * pl + c] = Lown_g[i];
+        aLA[i * pl + c] = Lgp[i];
+        aLA[(15 + i) * pl + c] = Lown_g[i];
     }
     // the flow planes only for a node liquid at k+1 (the gather reads them
     // only there), u^k only for a node liquid at k; a node solid at k+1
@@ -557,19 +582,19 @@ __global__ __launch_bounds__(TX * TY) void k_adj_step(Geom G, Phys P, AdjBufs B)
     if (liq1) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            B.la[(5 + i) * pl + c] = Ld[i];
-            B.la[(20 + i) * pl + c] = Lown_d[i];
+            aLA[(5 + i) * pl + c] = Ld[i];
+            aLA[(20 + i) * pl + c] = Lown_d[i];
         }
-        B.la[14 * pl + c] = Lrb;
-        B.ga[pl + c] = ga1 + LAc;
-        B.ga[2 * pl + c] = ga2 + LBc;
+        aLA[14 * pl + c] = Lrb;
+        aGA[pl + c] = ga1 + LAc;
+        aGA[2 * pl + c] = ga2 + LBc;
     }
     if (liqk) {  // u^k also enters the wall extrapolation of g
-        B.la[30 * pl + c] = Luxk;
-        B.la[31 * pl + c] = Luyk;
+        aLA[30 * pl + c] = Luxk;
+        aLA[31 * pl + c] = Luyk;
     }
-    B.la[29 * pl + c] = Lflk;
-    if (acc_eps) B.ga[c] = ga0 + Leps;
+    aLA[29 * pl + c] = Lflk;
+    if (acc_eps) aGA[c] = ga0 + Leps;
 }
 
 // Terminal adjoint of a loss of the final fields: T = sum of g+, so every
@@ -630,14 +655,27 @@ hipError_t launch_adjoint_step(const Geom& G, const Phys& P, const AdjBufs& B, b
                                bool first, hipStream_t s)
 {
     const dim3 grd(tile_blocks(G, TY)), blk(TX, TY);
+    // 32-bit offsets while the largest array (the local adjoints) indexes
+    // below 2^30 elements
+    if ((uint64_t)ADJ_LA * (uint64_t)G.plane < (1ull << 30)) {
+        if (flow && first)
+            hipLaunchKernelGGL((k_adj_step<true, true, true>), grd, blk, 0, s, G, P, B);
+        else if (flow)
+            hipLaunchKernelGGL((k_adj_step<true, false, true>), grd, blk, 0, s, G, P, B);
+        else if (first)
+            hipLaunchKernelGGL((k_adj_step<false, true, true>), grd, blk, 0, s, G, P, B);
+        else
+            hipLaunchKernelGGL((k_adj_step<false, false, true>), grd, blk, 0, s, G, P, B);
+        return hipGetLastError();
+    }
     if (flow && first)
-        hipLaunchKernelGGL((k_adj_step<true, true>), grd, blk, 0, s, G, P, B);
+        hipLaunchKernelGGL((k_adj_step<true, true, false>), grd, blk, 0, s, G, P, B);
     else if (flow)
-        hipLaunchKernelGGL((k_adj_step<true, false>), grd, blk, 0, s, G, P, B);
+        hipLaunchKernelGGL((k_adj_step<true, false, false>), grd, blk, 0, s, G, P, B);
     else if (first)
-        hipLaunchKernelGGL((k_adj_step<false, true>), grd, blk, 0, s, G, P, B);
+        hipLaunchKernelGGL((k_adj_step<false, true, false>), grd, blk, 0, s, G, P, B);
     else
-        hipLaunchKernelGGL((k_adj_step<false, false>), grd, blk, 0, s, G, P, B);
+        hipLaunchKernelGGL((k_adj_step<false, false, false>), grd, blk, 0, s, G, P, B);
     return hipGetLastError();
 }
 
