@@ -582,8 +582,8 @@ def main():
                     help="with --ablation: one horizon, this Fourier number, all readings")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (the "
-              "multi-GPU design is described, not built)" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported (the "
+              "multi-GPU sharding is designed, not implemented)" % args.gpus, file=sys.stderr)
         return 2
     if args.ablation:
         return ablation(((args.ablation_fo, True),)) if args.ablation_fo > 0 else ablation()
