@@ -86,25 +86,29 @@ void k_batch_step(BatchArgs a)
     }
 }
 
-// Waves of a two-step block in a batch: tiles of 62 x 10 nodes (a narrow
-// last column of a cavity: 30 x 22).  Taller than the single lattice's (8
-// waves, 62 x 6): measured 3 % faster on the 512-cavity workload (531
-// against 548 us per step) and 2 % on batches of 512^2 cavities.
+// Waves of a two-step block in a batch: tiles of 62 x 6 nodes, as on a
+// single lattice (a narrow last column of a cavity: 30 x 14).  With the
+// per-node code of the cavity form the 8-wave blocks hold 48 VGPRs and 88
+// SGPRs, four blocks per CU, and measured 3 % faster on the 512-cavity
+// workload than 12-wave blocks at two per CU (430 against 444 us per step;
+// 457 against 474 with general thermal properties).  Before that form the
+// 12-wave blocks were 3 % faster (531 against 548).
 #ifndef DMRT_B2_WAVES
-#define DMRT_B2_WAVES 12
+#define DMRT_B2_WAVES 8
 #endif
 #ifndef DMRT_B2_OCC
-#define DMRT_B2_OCC 6
+#define DMRT_B2_OCC 7
 #endif
 constexpr int B2_WAVES = DMRT_B2_WAVES;
 
 // Two steps of one tile of the list per block: block b works on die b % 8,
 // tile a.die[die] + b / 8 of that die's part.  IO: BufIOT, or WinIOT with
-// the window pair of the two halves of the state arena, compiled for 6
-// waves per SIMD (two 12-wave blocks per CU, as the LDS allows); at 8-wave
-// blocks and 7 waves per SIMD this took 94 scalar registers with 15 spilled
-// (106 with 23 spilled for BufIOT) and measured 4.6 % faster on the batch of
-// 512 cavities; without the bound 0.8 %, with a bound of 8 slower.  UT:
+// the window pair of the two halves of the state arena, compiled for
+// DMRT_B2_OCC waves per SIMD (7 for 8-wave blocks, 6 for 12-wave ones, as
+// the LDS allows); the window pair took 94 scalar registers with 15
+// spilled (106 with 23 spilled for BufIOT) in the general build and
+// measured 4.6 % faster on the batch of 512 cavities; without the bound
+// 0.8 %, with a bound of 8 slower.  UT:
 // every cavity has the cavity form of tile_step2 (uniform thermal
 // properties, walls on every side).
 template <class IO, bool UT = false>
