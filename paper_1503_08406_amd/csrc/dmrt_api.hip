@@ -1337,6 +1337,7 @@ struct dmrt_batch {
     // tile list cut into die parts, launched with one block per tile
     bool two_ok = false, two = false;
     bool per_array = false;  // one buffer resource per array (addressing 1)
+    bool cavity_form = false;  // every cavity: uniform thermal properties, walls all round
     int4* dtiles2 = nullptr;
     int die2[dmrtk::NXCD + 1]{};
     int blocks2 = 0;
@@ -1487,10 +1488,7 @@ dmrtk::BatchArgs batch_args(const dmrt_batch* b, int p, bool two = false)
     a.win = (const char*)b->f[p];
     a.wout = (const char*)b->f[1 - p];
     a.win_bytes = !b->per_array && half < (1ull << 32) ? (uint32_t)half : 0u;
-    a.uniform_thermal = 1;
-    for (const dmrtk::Cavity& c : b->cav)
-        if (!c.P.zeta_uniform || c.P.dsig != 0.0f || c.G.per_x || c.G.per_y)
-            a.uniform_thermal = 0;
+    a.uniform_thermal = b->cavity_form ? 1 : 0;
     return a;
 }
 
@@ -1713,6 +1711,9 @@ int dmrt_batch_create(int32_t ncav, const dmrt_cavity* cav, const dmrt_opts* opt
     if ((rc = batch_layout(b, o.block_rows ? o.block_rows : 4, 0))) return bail(rc);
     b->two_ok = o.steps_per_launch == 2;
     b->per_array = o.addressing == 1;
+    b->cavity_form = true;
+    for (const dmrtk::Cavity& c : b->cav)
+        if (!c.P.zeta_uniform || c.P.dsig != 0.0f || c.G.per_x || c.G.per_y) b->cavity_form = false;
     if (b->two_ok && (rc = batch_layout2(b))) return bail(rc);
     b->two = b->two_ok;
     *out = b;
